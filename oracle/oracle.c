@@ -1,0 +1,499 @@
+/*
+ * oracle.c -- serial FP64 mixed rejection KMC for the 2D lattice Coulomb glass.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain loops, no blocking or fusion;
+ * every function names the passage of the paper it follows.  Build:
+ *   gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared oracle.c -lm
+ * (contraction off so that a*b+c is never fused: the order of every rounding is
+ * the one written here).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int32_t g_mutation = 0;
+void or_set_mutation(int32_t m) { g_mutation = m; }
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based RNG the
+ * paper uses for its many parallel streams (section "Hopping conduction",
+ * implementation paragraph).  Round: two 32x32->64 products of counter words 0
+ * and 2 with the multipliers, outputs permuted and xored with the key; the key
+ * is bumped by the Weyl constants between rounds.                              */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3 };
+
+static void stream(const or_state* st, uint64_t idx, uint32_t tag, uint32_t w[4]);
+
+/* uniform in (0,1) on the grid (2k+1) 2^-53, k a 52-bit integer from two words */
+static double unit52(uint32_t hi, uint32_t lo) {
+  uint64_t k = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+  return (double)(2u * k + 1u) * 0x1p-53;
+}
+
+/* ------------------------------------------------------------------------- */
+struct or_state {
+  or_params p;
+  int32_t N;
+  double nu;
+  /* proposal law */
+  int32_t n_orb, n_vec;
+  int32_t* orb_r2;
+  int32_t* orb_size;
+  int32_t* orb_first;
+  uint64_t* thr;
+  int32_t* vec_dx;
+  int32_t* vec_dy;
+  double wsum, Gamma;
+  /* 1/r by separation: invr[(ddy mod L) * L + (ddx mod L)] */
+  double* invr;
+  /* configuration */
+  uint8_t* n;
+  double* phi;
+  double* eps;
+  uint64_t s_last, s_scan, hops, theta_pass;
+  int64_t P;
+  double t, H0;
+};
+
+static void stream(const or_state* st, uint64_t idx, uint32_t tag, uint32_t w[4]) {
+  uint32_t ctr[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), st->p.sample_id, tag};
+  uint32_t key[2] = {(uint32_t)st->p.seed, (uint32_t)(st->p.seed >> 32)};
+  or_philox(ctr, key, w);
+}
+
+static int32_t wrap(int32_t a, int32_t L) {
+  int32_t r = a % L;
+  return r < 0 ? r + L : r;
+}
+
+/* Minimum-image distance on the torus (section "Results ... two dimensions":
+ * toroidal boundaries, minimal image convention for r_ij and dx_ij). */
+static double invr_def(int32_t L, int32_t ddx, int32_t ddy) {
+  int32_t a = wrap(ddx, L), b = wrap(ddy, L);
+  if (L - a < a) a = L - a;
+  if (L - b < b) b = L - b;
+  int32_t r2 = a * a + b * b;
+  if (r2 == 0) return 0.0;
+  return 1.0 / sqrt((double)r2);
+}
+
+double or_invr(const or_state* st, int32_t ddx, int32_t ddy) {
+  int32_t L = st->p.L;
+  return st->invr[wrap(ddy, L) * L + wrap(ddx, L)];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Proposal law of the mixed algorithm: Q ~ Gamma^T_ij = exp(-2 r_ij / xi), which
+ * on a lattice depends only on the displacement (section "Hopping conduction",
+ * mixed algorithm and lattice paragraph).  Displacements with |d| <= rc are
+ * grouped in orbits of the square's symmetry group (all (+-a,+-b), (+-b,+-a));
+ * members of an orbit share r and therefore weight.  Tower sampling over the
+ * cumulative orbit weights picks the orbit, a uniform member picks d.          */
+typedef struct { int32_t a, b, r2; } orbit_rep;
+
+static int cmp_rep(const void* x, const void* y) {
+  const orbit_rep* p = (const orbit_rep*)x;
+  const orbit_rep* q = (const orbit_rep*)y;
+  if (p->r2 != q->r2) return p->r2 < q->r2 ? -1 : 1;
+  if (p->b != q->b) return p->b < q->b ? -1 : 1;
+  return 0;
+}
+
+typedef struct { int32_t dx, dy; } vec2;
+
+static int cmp_vec(const void* x, const void* y) {
+  const vec2* p = (const vec2*)x;
+  const vec2* q = (const vec2*)y;
+  if (p->dy != q->dy) return p->dy < q->dy ? -1 : 1;
+  if (p->dx != q->dx) return p->dx < q->dx ? -1 : 1;
+  return 0;
+}
+
+static int build_tower(or_state* st) {
+  const double rc = st->p.rc, xi = st->p.xi;
+  int32_t amax = (int32_t)floor(rc) + 1;
+  int32_t cap = (amax + 1) * (amax + 1);
+  orbit_rep* reps = (orbit_rep*)malloc(sizeof(orbit_rep) * (size_t)cap);
+  if (!reps) return -2;
+  int32_t n = 0;
+  for (int32_t a = 1; a <= amax; ++a)
+    for (int32_t b = 0; b <= a; ++b)
+      if ((double)(a * a + b * b) <= rc * rc) {
+        reps[n].a = a; reps[n].b = b; reps[n].r2 = a * a + b * b; ++n;
+      }
+  if (n == 0) { free(reps); return -1; }
+  qsort(reps, (size_t)n, sizeof(orbit_rep), cmp_rep);
+
+  st->n_orb = n;
+  st->orb_r2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  st->orb_size = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  st->orb_first = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  st->thr = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+  st->vec_dx = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * 8);
+  st->vec_dy = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * 8);
+  double* cum = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!st->orb_r2 || !st->orb_size || !st->orb_first || !st->thr || !st->vec_dx ||
+      !st->vec_dy || !cum) { free(reps); free(cum); return -2; }
+
+  int32_t nv = 0;
+  double acc = 0.0;
+  for (int32_t o = 0; o < n; ++o) {
+    int32_t a = reps[o].a, b = reps[o].b;
+    vec2 cand[8] = {{a, b}, {-a, b}, {a, -b}, {-a, -b}, {b, a}, {-b, a}, {b, -a}, {-b, -a}};
+    vec2 uniq[8];
+    int32_t nu = 0;
+    for (int k = 0; k < 8; ++k) {
+      int dup = 0;
+      for (int q = 0; q < nu; ++q)
+        if (uniq[q].dx == cand[k].dx && uniq[q].dy == cand[k].dy) dup = 1;
+      if (!dup) uniq[nu++] = cand[k];
+    }
+    qsort(uniq, (size_t)nu, sizeof(vec2), cmp_vec);
+    st->orb_r2[o] = reps[o].r2;
+    st->orb_size[o] = nu;
+    st->orb_first[o] = nv;
+    for (int32_t q = 0; q < nu; ++q) {
+      st->vec_dx[nv] = uniq[q].dx;
+      st->vec_dy[nv] = uniq[q].dy;
+      ++nv;
+    }
+    double r = sqrt((double)reps[o].r2);
+    double w = (g_mutation == 6) ? (double)nu * exp(-1.0 * r / xi)
+                                 : (double)nu * exp(-2.0 * r / xi);
+    acc = acc + w;
+    cum[o] = acc;
+  }
+  st->n_vec = nv;
+  st->wsum = acc;
+  for (int32_t o = 0; o + 1 < n; ++o)
+    st->thr[o] = (uint64_t)floor(ldexp(cum[o] / acc, 32));
+  st->thr[n - 1] = (uint64_t)1 << 32;
+  /* Gamma = sum_i sum_{j != i} Gamma^T_ij = N * sum_d exp(-2|d|/xi) */
+  st->Gamma = (double)st->N * acc;
+  free(reps);
+  free(cum);
+  return 0;
+}
+
+void or_draw(const or_state* st, uint64_t s, int32_t* i, int32_t* v, double* u) {
+  uint32_t w[4];
+  stream(st, s, TAG_PROPOSE, w);
+  *i = (int32_t)(((uint64_t)w[0] * (uint64_t)st->N) >> 32);
+  int32_t o = 0;
+  while (!((uint64_t)w[1] < st->thr[o])) ++o;
+  uint32_t member = (g_mutation == 5) ? 0u : (w[3] & (uint32_t)(st->orb_size[o] - 1));
+  *v = st->orb_first[o] + (int32_t)member;
+  *u = unit52(w[2], w[3]);
+}
+
+double or_vec_prob(const or_state* st, int32_t v) {
+  int32_t o = 0;
+  while (!(v < st->orb_first[o] + st->orb_size[o])) ++o;
+  uint64_t lo = (o == 0) ? 0 : st->thr[o - 1];
+  double po = (double)(st->thr[o] - lo) * 0x1p-32;
+  return po / (double)st->orb_size[o];
+}
+
+/* ------------------------------------------------------------------------- */
+/* eps_l = phi_l + sum_{m != l} (n_m - nu) / r_lm, summed over m = 0..N-1 in order
+ * (definition of the single-particle energies after Eq. 2).                     */
+static void eps_from_occ(const or_state* st, double* out) {
+  const int32_t L = st->p.L, N = st->N;
+  for (int32_t l = 0; l < N; ++l) {
+    int32_t xl = l % L, yl = l / L;
+    double acc = st->phi[l];
+    for (int32_t m = 0; m < N; ++m) {
+      if (m == l) continue;
+      double q = (g_mutation == 7) ? (double)st->n[m] : (double)st->n[m] - st->nu;
+      acc = acc + q * or_invr(st, xl - m % L, yl - m / L);
+    }
+    out[l] = acc;
+  }
+}
+
+void or_recompute_eps(const or_state* st, double* out) { eps_from_occ(st, out); }
+
+/* Field-free part of Eq. 1: sum_i phi_i n_i + 1/2 sum_{i != j} (n_i-nu)(n_j-nu)/r_ij. */
+double or_energy(const or_state* st) {
+  const int32_t L = st->p.L, N = st->N;
+  double h1 = 0.0, h2 = 0.0;
+  for (int32_t i = 0; i < N; ++i) h1 = h1 + st->phi[i] * (double)st->n[i];
+  for (int32_t i = 0; i < N; ++i) {
+    double qi = (double)st->n[i] - st->nu;
+    for (int32_t j = 0; j < N; ++j) {
+      if (j == i) continue;
+      double qj = (double)st->n[j] - st->nu;
+      h2 = h2 + qi * qj * or_invr(st, i % L - j % L, i / L - j / L);
+    }
+  }
+  return h1 + 0.5 * h2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Random initial configuration: the n_e sites with the smallest 64-bit Philox
+ * keys (ties by index) are occupied, i.e. a uniform n_e-subset; phi_i uniform in
+ * [-W, W] (Eq. 1 and the random-start runs of section "Results").              */
+typedef struct { uint64_t key; int32_t i; } site_key;
+
+static int cmp_key(const void* x, const void* y) {
+  const site_key* p = (const site_key*)x;
+  const site_key* q = (const site_key*)y;
+  if (p->key != q->key) return p->key < q->key ? -1 : 1;
+  return p->i < q->i ? -1 : (p->i > q->i);
+}
+
+int or_create(const or_params* p, or_state** out) {
+  *out = NULL;
+  if (p->L < 3 || p->L > 4096) return -1;
+  int32_t N = p->L * p->L;
+  if (p->n_e < 1 || p->n_e >= N) return -1;
+  if (!(p->T > 0.0) || !(p->xi > 0.0) || !(p->W >= 0.0)) return -1;
+  if (!(p->rc >= 1.0) || !(2.0 * p->rc < (double)p->L)) return -1;
+  if (p->clock_mode != 0 && p->clock_mode != 1) return -1;
+
+  or_state* st = (or_state*)calloc(1, sizeof(or_state));
+  if (!st) return -2;
+  st->p = *p;
+  st->N = N;
+  st->nu = (double)p->n_e / (double)N;
+  int rc = build_tower(st);
+  st->invr = (double*)malloc(sizeof(double) * (size_t)N);
+  st->n = (uint8_t*)calloc((size_t)N, 1);
+  st->phi = (double*)malloc(sizeof(double) * (size_t)N);
+  st->eps = (double*)malloc(sizeof(double) * (size_t)N);
+  site_key* keys = (site_key*)malloc(sizeof(site_key) * (size_t)N);
+  if (rc != 0 || !st->invr || !st->n || !st->phi || !st->eps || !keys) {
+    free(keys);
+    or_destroy(st);
+    return rc == -1 ? -1 : -2;
+  }
+  for (int32_t dy = 0; dy < p->L; ++dy)
+    for (int32_t dx = 0; dx < p->L; ++dx) st->invr[dy * p->L + dx] = invr_def(p->L, dx, dy);
+
+  for (int32_t i = 0; i < N; ++i) {
+    uint32_t w[4];
+    stream(st, (uint64_t)i, TAG_OCC, w);
+    keys[i].key = ((uint64_t)w[0] << 32) | (uint64_t)w[1];
+    keys[i].i = i;
+  }
+  qsort(keys, (size_t)N, sizeof(site_key), cmp_key);
+  for (int32_t k = 0; k < p->n_e; ++k) st->n[keys[k].i] = 1;
+  free(keys);
+
+  for (int32_t i = 0; i < N; ++i) {
+    uint32_t w[4];
+    stream(st, (uint64_t)i, TAG_PHI, w);
+    st->phi[i] = p->W * (2.0 * unit52(w[0], w[1]) - 1.0);
+  }
+  eps_from_occ(st, st->eps);
+  st->H0 = or_energy(st);
+  *out = st;
+  return 0;
+}
+
+void or_destroy(or_state* st) {
+  if (!st) return;
+  free(st->orb_r2); free(st->orb_size); free(st->orb_first); free(st->thr);
+  free(st->vec_dx); free(st->vec_dy); free(st->invr);
+  free(st->n); free(st->phi); free(st->eps);
+  free(st);
+}
+
+void or_dims(const or_state* st, int32_t* N, int32_t* n_orb, int32_t* n_vec) {
+  if (N) *N = st->N;
+  if (n_orb) *n_orb = st->n_orb;
+  if (n_vec) *n_vec = st->n_vec;
+}
+
+void or_tower(const or_state* st, uint64_t* thr, int32_t* orb_size, int32_t* orb_first,
+              int32_t* vec_dx, int32_t* vec_dy, double* wsum, double* Gamma) {
+  if (thr) memcpy(thr, st->thr, sizeof(uint64_t) * (size_t)st->n_orb);
+  if (orb_size) memcpy(orb_size, st->orb_size, sizeof(int32_t) * (size_t)st->n_orb);
+  if (orb_first) memcpy(orb_first, st->orb_first, sizeof(int32_t) * (size_t)st->n_orb);
+  if (vec_dx) memcpy(vec_dx, st->vec_dx, sizeof(int32_t) * (size_t)st->n_vec);
+  if (vec_dy) memcpy(vec_dy, st->vec_dy, sizeof(int32_t) * (size_t)st->n_vec);
+  if (wsum) *wsum = st->wsum;
+  if (Gamma) *Gamma = st->Gamma;
+}
+
+void or_get_occ(const or_state* st, uint8_t* out) { memcpy(out, st->n, (size_t)st->N); }
+void or_get_phi(const or_state* st, double* out) { memcpy(out, st->phi, sizeof(double) * (size_t)st->N); }
+void or_get_eps(const or_state* st, double* out) { memcpy(out, st->eps, sizeof(double) * (size_t)st->N); }
+
+void or_get_scalars(const or_state* st, or_scalars* out) {
+  out->s_last = st->s_last;
+  out->s_scan = st->s_scan;
+  out->hops = st->hops;
+  out->P = st->P;
+  out->t = st->t;
+  out->H0 = st->H0;
+  out->theta_pass = st->theta_pass;
+  out->Gamma = st->Gamma;
+}
+
+int or_set_occ(or_state* st, const uint8_t* n) {
+  int32_t c = 0;
+  for (int32_t i = 0; i < st->N; ++i) {
+    if (n[i] > 1) return -1;
+    c += n[i];
+  }
+  if (c != st->p.n_e) return -1;
+  memcpy(st->n, n, (size_t)st->N);
+  eps_from_occ(st, st->eps);
+  st->H0 = or_energy(st);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* dH_ij = eps_j - eps_i - 1/r_ij - E dx_ij (text after Eq. 2), evaluated in this
+ * order: ((eps_j - eps_i) - 1/r) - E*dx.                                        */
+static double delta_h(const or_state* st, int32_t i, int32_t j, int32_t v) {
+  double vij = or_invr(st, st->vec_dx[v], st->vec_dy[v]);
+  double dx = (double)st->vec_dx[v];
+  if (g_mutation == 1) return ((st->eps[j] - st->eps[i]) - vij) + st->p.E * dx;
+  if (g_mutation == 2) return (st->eps[j] - st->eps[i]) - st->p.E * dx;
+  return ((st->eps[j] - st->eps[i]) - vij) - st->p.E * dx;
+}
+
+static int32_t partner(const or_state* st, int32_t i, int32_t v) {
+  const int32_t L = st->p.L;
+  int32_t xj = wrap(i % L + st->vec_dx[v], L);
+  int32_t yj = wrap(i / L + st->vec_dy[v], L);
+  return yj * L + xj;
+}
+
+/* Acceptance of the mixed algorithm: Gamma^A_ij = theta_ij min(1, exp(-dH/T)),
+ * theta_ij = n_i (1 - n_j) (Eq. 2 and the factorisation that follows it).      */
+static double metropolis(const or_state* st, double dH) {
+  if (dH <= 0.0) return 1.0;
+  if (g_mutation == 8) return exp(-dH * st->p.T);
+  return exp(-dH / st->p.T);
+}
+
+double or_move(const or_state* st, int32_t i, int32_t v, double* dH) {
+  int32_t j = partner(st, i, v);
+  double d = delta_h(st, i, j, v);
+  if (dH) *dH = d;
+  if (!(st->n[i] == 1 && st->n[j] == 0)) return 0.0;
+  double a = metropolis(st, d);
+  return a > 1.0 ? 1.0 : a;
+}
+
+double or_acceptance(const or_state* st) {
+  /* P(site i) = #{w0 : floor(w0 N / 2^32) = i} / 2^32, exactly */
+  const uint64_t two32 = (uint64_t)1 << 32;
+  const uint64_t N = (uint64_t)st->N;
+  double acc = 0.0;
+  for (int32_t i = 0; i < st->N; ++i) {
+    uint64_t lo = ((uint64_t)i * two32 + N - 1) / N;
+    uint64_t hi = ((uint64_t)(i + 1) * two32 + N - 1) / N;
+    double pi = (double)(hi - lo) * 0x1p-32;
+    double s = 0.0;
+    for (int32_t v = 0; v < st->n_vec; ++v) s = s + or_vec_prob(st, v) * or_move(st, i, v, NULL);
+    acc = acc + pi * s;
+  }
+  return acc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Step 3b: after hop i -> j, eps_l += 1/r_lj - 1/r_li for every l, with
+ * 1/r(0) = 0 giving +1/r_ij at i and -1/r_ij at j.                             */
+static void update_eps(or_state* st, int32_t i, int32_t j) {
+  const int32_t L = st->p.L;
+  const int32_t xi = i % L, yi = i / L, xj = j % L, yj = j / L;
+  for (int32_t y = 0; y < L; ++y)
+    for (int32_t x = 0; x < L; ++x) {
+      int32_t l = y * L + x;
+      if (g_mutation == 3 && (l == i || l == j)) continue;
+      double a = or_invr(st, x - xj, y - yj), b = or_invr(st, x - xi, y - yi);
+      if (g_mutation == 10) st->eps[l] = st->eps[l] + (b - a);
+      else st->eps[l] = st->eps[l] + (a - b);
+    }
+}
+
+/* Clock: after each executed hop with m serial proposals since the previous
+ * one, t advances by m/Gamma (deterministic increment used for the conductivity
+ * figure) or by a Gaussian of mean m/Gamma and deviation sqrt(m)/Gamma (step 3c),
+ * clamped at zero.  The Gaussian uses Box-Muller on stream CLOCK, index = hop.  */
+static void advance_clock(or_state* st, uint64_t m) {
+  if (st->p.clock_mode == 0) {
+    st->t = (double)st->s_last / st->Gamma;
+    return;
+  }
+  uint32_t w[4];
+  stream(st, st->hops, TAG_CLOCK, w);
+  double u1 = unit52(w[0], w[1]), u2 = unit52(w[2], w[3]);
+  double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  double mean = (double)m / st->Gamma;
+  double sd = sqrt((double)m) / st->Gamma;
+  double dt = mean + sd * z;
+  if (dt < 0.0) dt = 0.0;
+  st->t = st->t + dt;
+}
+
+int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
+               uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap) {
+  int64_t done = 0, scanned = 0;
+  for (;;) {
+    if (n_hops > 0 && done >= n_hops) break;
+    if (t_end >= 0.0 && st->t >= t_end) break;
+    if (max_labels > 0 && scanned >= max_labels) break;
+    /* step 1: propose (i, j) with probability Gamma^T_ij / Gamma */
+    uint64_t s = st->s_scan + 1;
+    st->s_scan = s;
+    ++scanned;
+    int32_t i, v;
+    double u;
+    or_draw(st, s, &i, &v, &u);
+    int32_t j = partner(st, i, v);
+    /* step 2: accept with theta_ij min(1, exp(-dH/T)) */
+    if (g_mutation == 4) {
+      if (st->n[i] != 1) continue;
+    } else if (!(st->n[i] == 1 && st->n[j] == 0)) {
+      continue;
+    }
+    st->theta_pass++;
+    double dH = delta_h(st, i, j, v);
+    if (!(dH <= 0.0 || u < metropolis(st, dH))) continue;
+    /* step 3: execute the hop, update dipole, energies and clock */
+    double dH0 = (st->eps[j] - st->eps[i]) - or_invr(st, st->vec_dx[v], st->vec_dy[v]);
+    st->n[i] = 0;
+    st->n[j] = 1;
+    if (g_mutation == 9) st->P -= st->vec_dx[v];
+    else st->P += st->vec_dx[v];
+    st->H0 = st->H0 + dH0;
+    uint64_t m = s - st->s_last;
+    st->s_last = s;
+    st->hops++;
+    if (log_label && done < log_cap) {
+      log_label[done] = s;
+      log_i[done] = i;
+      log_j[done] = j;
+    }
+    update_eps(st, i, j);
+    advance_clock(st, m);
+    ++done;
+  }
+  return done;
+}
