@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the parallel-rejection KMC step for the 2D lattice Coulomb glass on one MI355X.
+
+Workload: a batch of B independent samples (default 256, one workgroup per sample) at
+L=128 (N=16384), half filling, W=1, xi=1, rc=10, T=0.02, E=0.005, Philox seed 3, sample ids
+0..B-1, from the random initial configuration.  A step is one pass of the whole hot path
+for every sample: `hops_per_step` accepted hops (proposal draw, occupancy filter,
+Metropolis, lowest-accepted-label selection, hop execution, local-energy update) and, in
+the FP32 form, the FP64 refresh that ends each refresh interval (default: the interval is
+the step).  The timed region starts with every input resident in HBM.
+
+The headline value is accepted hops/s of the FP32-with-FP64-refresh form; the plain FP64
+form is timed on the same samples and reported beside it.  The JSON line also carries the
+LDS roofline of the hop kernel (algorithmic bytes per launch / mean launch time from HIP
+events on the library's stream) and the CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# 256 CUs x 128 B/clk x 2.4 GHz: LDS bandwidth of the chip (see the measurement notes)
+LDS_PEAK_GBS = 256 * 128 * 2.4
+
+
+def _cpu_worker(args):
+    import oracle
+    from workloads import headline
+
+    b, hops, seed = args
+    s = headline(b + 1, seed=seed)[b]
+    o = oracle.Oracle(L=s.L, n_e=s.n_e, W=s.W, xi=s.xi, rc=s.rc, T=s.T, E=s.E, seed=s.seed,
+                      sample_id=s.sample_id)
+    t0 = time.perf_counter()
+    o.run(hops, log_cap=0)
+    return hops, time.perf_counter() - t0
+
+
+def cpu_baseline(hops: int, seed: int, cores: int) -> dict:
+    """The serial FP64 oracle on this host: one headline sample per process, `hops` hops
+    each from the random start, all processes concurrently; aggregate = sum of rates."""
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_cpu_worker, [(b, hops, seed) for b in range(cores)])
+    rate = sum(h / t for h, t in res)
+    return {"value": rate, "unit": "accepted hops/s", "cores": cores, "kind": "oracle",
+            "sample": f"serial FP64 oracle, L=128 T=0.02 E=0.005 rc=10, samples 0..{cores - 1}, "
+                      f"{hops} hops each from the random start, {cores} processes, rates summed"}
+
+
+def run_form(cg, torch, samples, precision, args, hops_per_step):
+    opts = cg.make_opts(precision=precision, M=args.M, block=args.block, K_refresh=args.K)
+    b = cg.Batch(samples, opts)
+    n = len(samples)
+    for _ in range(args.warmup):
+        b.run_hops(hops_per_step)
+    torch.cuda.synchronize()
+    before = [b.stats(k) for k in range(n)]
+    b.kernel_time()  # reset the event accumulators
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run_hops(hops_per_step)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hop_ms, hop_n, ref_ms, ref_n = b.kernel_time()
+    after = [b.stats(k) for k in range(n)]
+    hops = sum(a["hops"] - c["hops"] for a, c in zip(after, before))
+    props = sum(a["s_last"] - c["s_last"] for a, c in zip(after, before))
+    evald = sum(a["evaluated"] - c["evaluated"] for a, c in zip(after, before))
+    theta = sum(a["theta_pass"] - c["theta_pass"] for a, c in zip(after, before))
+    drift = max(a["max_drift"] for a in after)
+    b.close()
+    return dict(seconds=dt, hops=hops, proposals=props, evaluated=evald, theta=theta, hop_ms=hop_ms,
+                hop_launches=hop_n, refresh_ms=ref_ms, refresh_launches=ref_n, max_drift=drift)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--hops-per-step", type=int, default=4096)
+    ap.add_argument("--M", type=int, default=2048)
+    ap.add_argument("--block", type=int, default=1024)
+    ap.add_argument("--K", type=int, default=4096)
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--cpu-hops", type=int, default=3000)
+    ap.add_argument("--cpu-cores", type=int, default=0)
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (samples are independent; a batch would split across "
+              f"GPUs without communication); --gpus {args.gpus} is not supported", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1407_5026_amd as cg
+    from workloads import headline
+
+    cg.load()
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    samples = headline(args.batch)
+    N = samples[0].L ** 2
+    print(f"[bench] FP32+refresh: B={args.batch} L=128 hops/step={args.hops_per_step} "
+          f"steps={args.steps} warmup={args.warmup} M={args.M} block={args.block} K={args.K}",
+          file=sys.stderr, flush=True)
+    r32 = run_form(cg, torch, samples, cg.CG_FP32_REFRESH, args, args.hops_per_step)
+    print(f"[bench] FP32 done: {r32['hops'] / r32['seconds']:.4g} hops/s", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.skip_fp64:
+        r64 = run_form(cg, torch, samples, cg.CG_FP64, args, args.hops_per_step)
+        print(f"[bench] FP64 done: {r64['hops'] / r64['seconds']:.4g} hops/s", file=sys.stderr, flush=True)
+
+    value = r32["hops"] / r32["seconds"]
+    # LDS roofline of the hop kernel: per accepted hop the update reads and writes N energies
+    # (2 N s_eps bytes) and the proposals read 2 occupancy bytes per serial proposal plus two
+    # energies per proposal that passes the occupancy filter.
+    s_eps = 4
+    m_bar = r32["proposals"] / max(r32["hops"], 1)
+    th_bar = r32["theta"] / max(r32["evaluated"], 1)
+    bytes_per_hop = 2 * N * s_eps + m_bar * (2 + th_bar * 2 * s_eps)
+    per_launch_hops = r32["hops"] / max(r32["hop_launches"], 1)
+    mean_launch_s = r32["hop_ms"] / max(r32["hop_launches"], 1) * 1e-3
+    achieved = bytes_per_hop * per_launch_hops / mean_launch_s / 1e9
+    out = {
+        "metric": "accepted hops/s per GPU (L=128, T=0.02, batched) FP32+refresh vs FP64 PR",
+        "value": value,
+        "unit": "accepted hops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["seconds"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.batch} samples L=128 N=16384 half filling W=1 xi=1 rc=10 "
+                               f"T=0.02 E=0.005, {args.hops_per_step} hops per sample per step, "
+                               f"FP32 with FP64 refresh every {args.K} hops",
+                   "batch": args.batch, "L": 128, "M": args.M, "block": args.block,
+                   "K_refresh": args.K, "hops_per_step": args.hops_per_step},
+        "proposals_per_s": r32["proposals"] / r32["seconds"],
+        "evaluated_labels_per_s": r32["evaluated"] / r32["seconds"],
+        "fp32_max_drift": r32["max_drift"],
+        "refresh_ms_per_step": r32["refresh_ms"] / args.steps,
+        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "kernel": "k_hops<float>", "bytes_per_hop": bytes_per_hop,
+                     "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
+    }
+    if r64 is not None:
+        out["fp64_value"] = r64["hops"] / r64["seconds"]
+        out["fp64_ms_per_step"] = r64["seconds"] / args.steps * 1e3
+    if not args.skip_cpu:
+        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_hops, samples[0].seed, cores)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,153 @@
+/*
+ * cgkmc.h -- C ABI of the MI355X parallel-rejection kinetic Monte Carlo library for
+ * electron hopping in the two-dimensional lattice Coulomb glass.
+ *
+ * Model (Ferrero, Kolton, Palassini, section "Hopping conduction in the Coulomb
+ * glass", Eq. 1 and Eq. 2): N = L*L sites on a torus, occupations n_i in {0,1} with
+ * n_electrons = nu*N electrons, random site energies phi_i uniform in [-W, W],
+ * Coulomb 1/r under the minimum-image convention, field E along +x.  Hops i -> j are
+ * proposed with probability proportional to exp(-2 r_ij / xi) for |d| <= rc (tower
+ * sampling), accepted with theta_ij min(1, exp(-dH/T)) where
+ * dH = eps_j - eps_i - 1/r_ij - E dx, and the lowest-labelled accepted proposal of a
+ * parallel iteration is executed (section "Parallel rejection algorithm", steps 1-3,
+ * and the mixed parallel-rejection algorithm, steps 1, 2, 3a-3c).  After a hop every
+ * local energy is updated (step 3b).
+ *
+ * Random numbers: Philox4x32-10 keyed by the sample's seed; proposal label s (1-based,
+ * counted from the creation of the sample) uses counter (s_lo, s_hi, sample_id, 0).
+ * Labels beyond the executed one in a parallel iteration are re-used against the new
+ * configuration, so the executed hop sequence equals that of the serial mixed
+ * algorithm for any parallel width M (the paper states the two are mathematically
+ * equivalent; with label-indexed numbers the equivalence holds path by path).
+ *
+ * Memory and streams: every device buffer lives in one caller-owned arena (device
+ * memory, size from cg_arena_bytes, alignment 256 bytes) that must outlive the
+ * context; the library allocates no device memory.  All work is enqueued on the HIP
+ * stream given at creation, in stream order.  Getters copy to caller-owned host
+ * memory and synchronise that stream.  A context is not thread-safe.
+ *
+ * Errors: functions return CG_OK (0) or a negative code; cg_last_error() returns a
+ * thread-local message describing the last failure.
+ */
+#ifndef CGKMC_H
+#define CGKMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CG_OK 0
+#define CG_EINVAL (-1)   /* invalid argument (rc >= L/2, T <= 0, bad index, ...)        */
+#define CG_ENOSPC (-2)   /* arena too small, or a sample does not fit the kernel's LDS */
+#define CG_EHIP (-3)     /* HIP runtime error; message in cg_last_error()                */
+#define CG_ESTALL (-4)   /* label cap reached before the requested hops; state is valid */
+
+#define CG_FP64 0          /* proposals, acceptance and energy update in FP64            */
+#define CG_FP32_REFRESH 1  /* FP32 proposals/update, FP64 O(N^2) refresh every K hops    */
+
+#define CG_CLOCK_DET 0    /* dt = m / Gamma (deterministic increment)                    */
+#define CG_CLOCK_GAUSS 1  /* dt ~ Gaussian(m/Gamma, sqrt(m)/Gamma), clamped at 0 (step 3c) */
+
+/* One independent sample (disorder realisation / temperature / size).
+ * Requirements: 3 <= L, L*L <= 65536; 1 <= n_electrons < L*L; W >= 0; xi > 0;
+ * 1 <= rc < L/2 (hops longer than L/2 are excluded, section "Results ... two
+ * dimensions"); T > 0. */
+typedef struct cg_sample_desc {
+  int32_t L;
+  int32_t n_electrons;
+  double W;
+  double xi;
+  double rc;
+  double T;
+  double E;
+  uint64_t seed;
+  uint32_t sample_id;
+  uint32_t reserved; /* set to 0 */
+} cg_sample_desc;
+
+typedef struct cg_run_opts {
+  int32_t precision;   /* CG_FP64 or CG_FP32_REFRESH                                    */
+  int32_t M;           /* labels per parallel iteration: block * {1,2,4,8}; 0 = block   */
+  int32_t block;       /* threads per workgroup: 256, 512 or 1024; 0 = 1024              */
+  int32_t K_refresh;   /* FP32 form: hops between FP64 refreshes (>= 1); 0 = 4096       */
+  int32_t clock_mode;  /* CG_CLOCK_DET or CG_CLOCK_GAUSS                                 */
+  int32_t log_hops;    /* per-sample capacity of the executed-hop log (0 = no log)       */
+  uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
+} cg_run_opts;
+
+/* Per-sample counters and observables. */
+typedef struct cg_stats {
+  uint64_t hops;        /* executed hops since creation                                 */
+  uint64_t s_last;      /* label of the last executed hop (0 before the first)          */
+  uint64_t s_scan;      /* every label <= s_scan has been decided                       */
+  int64_t P;            /* dipole moment change: sum of executed dx                     */
+  double t;             /* simulated clock (units of tau_0)                             */
+  double H0;            /* field-free energy of Eq. 1 (FP64 total)                      */
+  uint64_t sum_p;       /* sum over hops of the parallel iterations p = ceil(m / M)     */
+  uint64_t rounds;      /* barrier-separated evaluation rounds executed by the kernel   */
+  uint64_t evaluated;   /* label evaluations, re-evaluations after a hop included       */
+  uint64_t theta_pass;  /* evaluations that passed the occupancy filter                 */
+  uint64_t refreshes;   /* FP64 refreshes done (FP32 form)                              */
+  double max_drift;     /* max over refreshes of max_l |eps32_l - eps64_l|              */
+  double last_drift;    /* the same for the most recent refresh                         */
+  int32_t status;       /* CG_OK, or CG_ESTALL if the label cap stopped this sample     */
+  int32_t since_refresh;/* hops since the last refresh (FP32 form)                      */
+  int64_t logged;       /* entries written to the hop log                              */
+} cg_stats;
+
+typedef struct cg_ctx cg_ctx;
+
+/* Device bytes needed for n samples under the given options (alignment 256). */
+int cg_arena_bytes(const cg_sample_desc* samples, int32_t n, const cg_run_opts* opts,
+                   size_t* bytes);
+
+/* Build tables, draw the random initial occupation (a uniform n_electrons-subset) and
+ * the disorder phi, and compute the initial local energies
+ *   eps_l = phi_l + sum_{m != l} (n_m - nu) / r_lm
+ * in FP64 with m summed in index order, all on the GPU.  `arena` is device memory of
+ * at least cg_arena_bytes; `hip_stream` is a hipStream_t (NULL = default stream).
+ * Returns CG_OK and *out, or an error (no context is created). */
+int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_run_opts* opts,
+              void* arena, size_t arena_bytes, void* hip_stream);
+int cg_destroy(cg_ctx* ctx);
+
+/* Every sample executes exactly n_hops more hops (n_hops >= 1).  Returns CG_ESTALL if a
+ * sample reached max_labels_per_call first (its state stays consistent; call again). */
+int cg_run_hops(cg_ctx* ctx, int64_t n_hops);
+/* Every sample runs until the first hop that brings its clock to t >= t_end (samples
+ * already there execute nothing).  Returns CG_ESTALL as above. */
+int cg_run_time(cg_ctx* ctx, double t_end);
+/* FP32 form: refresh every sample now (FP64 O(N^2) recompute, drift recorded). */
+int cg_refresh(cg_ctx* ctx);
+
+/* Set temperature and field of one sample (T > 0). */
+int cg_set_TE(cg_ctx* ctx, int32_t sample, double T, double E);
+
+/* Host copies: occupation (N bytes), local energies as FP64 (N doubles; the FP32 form
+ * widens), disorder phi (N doubles), counters. */
+int cg_get_occupation(cg_ctx* ctx, int32_t sample, uint8_t* host_out);
+int cg_get_local_energies(cg_ctx* ctx, int32_t sample, double* host_out);
+int cg_get_phi(cg_ctx* ctx, int32_t sample, double* host_out);
+int cg_get_stats(cg_ctx* ctx, int32_t sample, cg_stats* out);
+/* Clock and current: t, dipole change P and sigma = P / (N E t) (0 if E t == 0). */
+int cg_get_current(cg_ctx* ctx, int32_t sample, double* t, int64_t* P, double* sigma);
+/* Executed-hop log of one sample: labels, origin and destination sites, up to `cap`
+ * entries; *count receives the number copied. */
+int cg_get_hop_log(cg_ctx* ctx, int32_t sample, uint64_t* labels, int32_t* from, int32_t* to,
+                   int64_t cap, int64_t* count);
+
+/* Device time of the hop kernel launches since the last call (ms) and launch count;
+ * resets both.  Timing uses HIP events on the context stream. */
+int cg_take_kernel_time(cg_ctx* ctx, double* hop_ms, int64_t* hop_launches, double* refresh_ms,
+                        int64_t* refresh_launches);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* cg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,823 @@
+// cgkmc.hip -- host side of libcgkmc: validation, proposal tables, arena plan, launches.
+//
+// The C ABI is declared in include/cgkmc.h.  All device memory comes from the caller's
+// arena; all work goes to the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "cgkmc.h"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+using namespace cg;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int set_err(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return set_err(CG_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
+                     __LINE__);                                                           \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+// ---------------------------------------------------------------------------------
+// Proposal law of the mixed algorithm on the lattice: displacements d with
+// 0 < |d|^2 <= rc^2, weight exp(-2|d|/xi) (section "Hopping conduction", mixed algorithm
+// and lattice implementation paragraph).  They are grouped in orbits of the square's
+// symmetry group -- all (+-a,+-b), (+-b,+-a) -- ordered by (|d|^2, smaller coordinate);
+// members within an orbit in ascending (dy, dx).  Tower sampling: the orbit is the
+// first o with w1 < thr[o], thr[o] = floor(2^32 * cumulative weight / total); the
+// member is w3 & (size - 1) (sizes are 4 or 8).
+struct HostTables {
+  int32_t n_orb = 0, n_vec = 0, H = 0;
+  std::vector<uint32_t> thr, orb;
+  std::vector<int32_t> vec;
+  std::vector<uint8_t> guide;
+  std::vector<double> tab64;  // full folded table
+  std::vector<double> tabk64;
+  std::vector<float> tabk32;
+  double wsum = 0.0, Gamma = 0.0;
+};
+
+struct Rep {
+  int32_t a, b, r2;
+};
+
+int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, HostTables& t) {
+  const double rc = d.rc, xi = d.xi;
+  const int32_t L = d.L, N = L * L;
+  std::vector<Rep> reps;
+  const int32_t amax = (int32_t)std::floor(rc) + 1;
+  for (int32_t a = 1; a <= amax; ++a)
+    for (int32_t b = 0; b <= a; ++b)
+      if ((double)(a * a + b * b) <= rc * rc) reps.push_back({a, b, a * a + b * b});
+  std::sort(reps.begin(), reps.end(), [](const Rep& p, const Rep& q) {
+    return p.r2 != q.r2 ? p.r2 < q.r2 : p.b < q.b;
+  });
+  const int32_t n_orb = (int32_t)reps.size();
+  if (n_orb < 1 || n_orb > 255)
+    return set_err(CG_EINVAL, "hop cutoff rc=%g gives %d displacement orbits (1..255 supported)",
+                   rc, n_orb);
+  t.n_orb = n_orb;
+  t.thr.assign(n_orb, 0u);
+  t.orb.assign(n_orb, 0u);
+  t.vec.clear();
+  std::vector<double> cum(n_orb);
+  double acc = 0.0;
+  for (int32_t o = 0; o < n_orb; ++o) {
+    const int32_t a = reps[o].a, b = reps[o].b;
+    std::vector<std::pair<int32_t, int32_t>> m;  // (dy, dx)
+    const int32_t cand[8][2] = {{a, b}, {-a, b}, {a, -b}, {-a, -b}, {b, a}, {-b, a}, {b, -a}, {-b, -a}};
+    for (auto& c : cand) {
+      std::pair<int32_t, int32_t> p(c[1], c[0]);
+      if (std::find(m.begin(), m.end(), p) == m.end()) m.push_back(p);
+    }
+    std::sort(m.begin(), m.end());
+    const int32_t size = (int32_t)m.size();
+    t.orb[o] = (uint32_t)t.vec.size() | ((uint32_t)(size - 1) << 16);
+    for (auto& p : m) t.vec.push_back((int32_t)((uint32_t)(p.second & 0xffff) | ((uint32_t)p.first << 16)));
+    const double r = std::sqrt((double)reps[o].r2);
+    const double w = (double)size * std::exp(-2.0 * r / xi);
+    acc = acc + w;
+    cum[o] = acc;
+  }
+  t.n_vec = (int32_t)t.vec.size();
+  for (int32_t o = 0; o + 1 < n_orb; ++o) {
+    const double c = std::floor(std::ldexp(cum[o] / acc, 32));
+    if (!(c < 4294967296.0))
+      return set_err(CG_EINVAL, "rc=%g: orbit weights beyond %d are below the 2^-32 resolution", rc, o);
+    t.thr[o] = (uint32_t)(uint64_t)c;
+  }
+  t.thr[n_orb - 1] = 0xffffffffu;  // never compared: the last orbit takes the rest
+  t.wsum = acc;
+  t.Gamma = (double)N * acc;
+  // guide: orbit of the smallest w1 in each bucket of width 2^(32 - kGuideBits)
+  t.guide.assign(kGuideSize, 0);
+  for (int32_t k = 0; k < kGuideSize; ++k) {
+    const uint64_t w = (uint64_t)k << (32 - kGuideBits);
+    int32_t o = 0;
+    while (o < n_orb - 1 && w >= (uint64_t)t.thr[o]) ++o;
+    t.guide[k] = (uint8_t)o;
+  }
+  // 1/r by folded separation (|dy|, |dx|), minimum image, 1/r(0) := 0
+  const int32_t H = L / 2, H1 = H + 1;
+  t.H = H;
+  t.tab64.assign((size_t)H1 * H1, 0.0);
+  for (int32_t ay = 0; ay < H1; ++ay)
+    for (int32_t ax = 0; ax < H1; ++ax) {
+      const int32_t r2 = ax * ax + ay * ay;
+      t.tab64[(size_t)ay * H1 + ax] = r2 == 0 ? 0.0 : 1.0 / std::sqrt((double)r2);
+    }
+  const size_t nk = layout == kTri ? (size_t)tri_entries(H) : (size_t)full_entries(H);
+  std::vector<double> k64(nk);
+  for (int32_t ay = 0; ay < H1; ++ay)
+    for (int32_t ax = 0; ax < H1; ++ax) {
+      size_t idx;
+      if (layout == kTri) {
+        const int32_t a = std::max(ay, ax), b = std::min(ay, ax);
+        idx = (size_t)(a * (a + 1) / 2 + b);
+      } else {
+        idx = (size_t)ay * H1 + ax;
+      }
+      k64[idx] = t.tab64[(size_t)ay * H1 + ax];
+    }
+  if (precision == CG_FP64) {
+    t.tabk64 = std::move(k64);
+  } else {
+    t.tabk32.resize(nk);
+    for (size_t k = 0; k < nk; ++k) t.tabk32[k] = (float)k64[k];
+  }
+  return CG_OK;
+}
+
+int32_t count_orbits(double rc) {
+  int32_t n = 0;
+  const int32_t amax = (int32_t)std::floor(rc) + 1;
+  for (int32_t a = 1; a <= amax; ++a)
+    for (int32_t b = 0; b <= a; ++b)
+      if ((double)(a * a + b * b) <= rc * rc) ++n;
+  return n;
+}
+
+int32_t count_vectors(double rc) {
+  int32_t n = 0;
+  const int32_t k = (int32_t)std::floor(rc) + 1;
+  for (int32_t dx = -k; dx <= k; ++dx)
+    for (int32_t dy = -k; dy <= k; ++dy)
+      if ((dx || dy) && (double)(dx * dx + dy * dy) <= rc * rc) ++n;
+  return n;
+}
+
+// ---------------------------------------------------------------------------------
+struct SampleLayout {
+  size_t st, tab64, tabk, thr, orb, vec, guide, static_end;  // uploaded in one copy
+  size_t eps, phi, occ, part, log_label, log_from, log_to, end;
+};
+
+struct Plan {
+  int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0;
+  int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, max_N = 0;
+  uint64_t max_labels = 1ull << 32;
+  size_t samples_off = 0, order_off = 0, scratch_off = 0, total = 0;
+  std::vector<SampleLayout> sl;
+  std::vector<int32_t> order;
+};
+
+int max_lds_bytes(int32_t* out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int v = 0, w = 0;
+  HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  if (hipDeviceGetAttribute(&w, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) w = 0;
+  *out = std::max(v, w);
+  return CG_OK;
+}
+
+int validate(const cg_sample_desc& d, int32_t b) {
+  const int32_t L = d.L;
+  if (L < 3 || L > 256 || L * L > 65536) return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 256]", b, L);
+  const int32_t N = L * L;
+  if (d.n_electrons < 1 || d.n_electrons >= N)
+    return set_err(CG_EINVAL, "sample %d: n_electrons=%d outside [1, N-1]", b, d.n_electrons);
+  if (!(d.W >= 0.0) || !std::isfinite(d.W)) return set_err(CG_EINVAL, "sample %d: W=%g", b, d.W);
+  if (!(d.xi > 0.0) || !std::isfinite(d.xi)) return set_err(CG_EINVAL, "sample %d: xi=%g", b, d.xi);
+  if (!(d.rc >= 1.0) || !(2.0 * d.rc < (double)L))
+    return set_err(CG_EINVAL, "sample %d: rc=%g must satisfy 1 <= rc < L/2 = %g", b, d.rc, 0.5 * L);
+  if (!(d.T > 0.0) || !std::isfinite(d.T)) return set_err(CG_EINVAL, "sample %d: T=%g must be > 0", b, d.T);
+  if (!std::isfinite(d.E)) return set_err(CG_EINVAL, "sample %d: E=%g", b, d.E);
+  return CG_OK;
+}
+
+int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p, bool query_lds) {
+  if (!s || n < 1 || n > 65535) return set_err(CG_EINVAL, "need 1..65535 samples (got %d)", n);
+  cg_run_opts def{};
+  if (!o) o = &def;
+  p.precision = o->precision;
+  if (p.precision != CG_FP64 && p.precision != CG_FP32_REFRESH)
+    return set_err(CG_EINVAL, "precision=%d", o->precision);
+  p.block = o->block ? o->block : 1024;
+  if (p.block != 256 && p.block != 512 && p.block != 1024)
+    return set_err(CG_EINVAL, "block=%d (256, 512 or 1024)", o->block);
+  p.M = o->M ? o->M : p.block;
+  if (p.M % p.block != 0) return set_err(CG_EINVAL, "M=%d is not a multiple of block=%d", o->M, p.block);
+  p.U = p.M / p.block;
+  if (p.U != 1 && p.U != 2 && p.U != 4 && p.U != 8)
+    return set_err(CG_EINVAL, "M/block=%d (1, 2, 4 or 8 labels per lane)", p.U);
+  p.K = o->K_refresh ? o->K_refresh : 4096;
+  if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
+  if (p.precision == CG_FP64) p.K = 0;
+  p.clock = o->clock_mode;
+  if (p.clock != CG_CLOCK_DET && p.clock != CG_CLOCK_GAUSS) return set_err(CG_EINVAL, "clock_mode=%d", p.clock);
+  if (o->log_hops < 0) return set_err(CG_EINVAL, "log_hops=%d", o->log_hops);
+  p.log_cap = o->log_hops;
+  p.max_labels = o->max_labels_per_call ? o->max_labels_per_call : (1ull << 32);
+  p.real_bytes = p.precision == CG_FP64 ? 8 : 4;
+
+  int32_t lds_cap = 163840;
+  if (query_lds) {
+    int rc = max_lds_bytes(&lds_cap);
+    if (rc != CG_OK) return rc;
+  }
+  // table layout: full (|dy|,|dx|) table if every sample fits, else the triangle
+  bool full_fits = true, tri_fits = true;
+  int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
+  for (int32_t b = 0; b < n; ++b) {
+    int rc = validate(s[b], b);
+    if (rc != CG_OK) return rc;
+    const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
+    const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
+    const int32_t f = hop_lds(N, NW, full_entries(H), n_vec, n_orb, p.real_bytes).total;
+    const int32_t t = hop_lds(N, NW, tri_entries(H), n_vec, n_orb, p.real_bytes).total;
+    need_full = std::max(need_full, f);
+    need_tri = std::max(need_tri, t);
+    full_fits = full_fits && f <= lds_cap;
+    tri_fits = tri_fits && t <= lds_cap;
+    need_exact = std::max(need_exact, align16(NW * 4) + full_entries(H) * 8);
+    max_N = std::max(max_N, N);
+  }
+  if (full_fits) {
+    p.layout = kFull;
+    p.lds_hop = need_full;
+  } else if (tri_fits) {
+    p.layout = kTri;
+    p.lds_hop = need_tri;
+  } else {
+    return set_err(CG_ENOSPC, "a sample needs %d bytes of LDS for its energies and tables (%d available)",
+                   need_tri, lds_cap);
+  }
+  if (need_exact + 2 * kInitBlock * 8 > lds_cap)
+    return set_err(CG_ENOSPC, "refresh kernel needs %d bytes of LDS", need_exact);
+  p.lds_exact = need_exact;
+  p.max_N = max_N;
+
+  size_t off = 0;
+  p.sl.resize(n);
+  for (int32_t b = 0; b < n; ++b) {
+    const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
+    const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
+    const int32_t ntab = p.layout == kTri ? tri_entries(H) : full_entries(H);
+    const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
+    SampleLayout& q = p.sl[b];
+    q.st = off;        off = align_up(off + sizeof(SampleState));
+    q.tab64 = off;     off = align_up(off + (size_t)full_entries(H) * 8);
+    q.tabk = off;      off = align_up(off + (size_t)full_entries(H) * p.real_bytes);
+    (void)ntab;
+    q.thr = off;       off = align_up(off + (size_t)n_orb * 4);
+    q.orb = off;       off = align_up(off + (size_t)n_orb * 4);
+    q.vec = off;       off = align_up(off + (size_t)n_vec * 4);
+    q.guide = off;     off = align_up(off + kGuideSize);
+    q.static_end = off;
+    q.eps = off;       off = align_up(off + (size_t)N * p.real_bytes);
+    q.phi = off;       off = align_up(off + (size_t)N * 8);
+    q.occ = off;       off = align_up(off + (size_t)NW * 4);
+    q.part = off;      off = align_up(off + (size_t)2 * nblk * 8);
+    q.log_label = off; off = align_up(off + (size_t)p.log_cap * 8);
+    q.log_from = off;  off = align_up(off + (size_t)p.log_cap * 4);
+    q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
+    q.end = off;
+  }
+  p.samples_off = off; off = align_up(off + sizeof(DevSample) * (size_t)n);
+  p.order_off = off;   off = align_up(off + sizeof(int32_t) * (size_t)n);
+  p.scratch_off = off; off = align_up(off + 64);
+  p.total = off;
+  // launch order: largest lattices first (a one-workgroup-per-sample batch finishes
+  // with its slowest sample)
+  p.order.resize(n);
+  for (int32_t b = 0; b < n; ++b) p.order[b] = b;
+  std::stable_sort(p.order.begin(), p.order.end(),
+                   [&](int32_t a, int32_t c) { return s[a].L > s[c].L; });
+  return CG_OK;
+}
+
+using HopFn = void (*)(const DevSample*, const int32_t*, RunArgs);
+
+template <typename R>
+HopFn pick_hop(int32_t U, int32_t layout) {
+  const bool tri = layout == kTri;
+  switch (U) {
+    case 1: return tri ? k_hops<R, 1, true> : k_hops<R, 1, false>;
+    case 2: return tri ? k_hops<R, 2, true> : k_hops<R, 2, false>;
+    case 4: return tri ? k_hops<R, 4, true> : k_hops<R, 4, false>;
+    default: return tri ? k_hops<R, 8, true> : k_hops<R, 8, false>;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+struct cg_ctx {
+  Plan plan;
+  std::vector<cg_sample_desc> desc;
+  std::vector<DevSample> dev;
+  uint8_t* arena = nullptr;
+  hipStream_t stream = nullptr;
+  DevSample* d_samples = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_pending = nullptr;
+  HopFn hop = nullptr;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_hop, ev_ref;
+  double acc_hop_ms = 0.0, acc_ref_ms = 0.0;
+  int64_t n_hop = 0, n_ref = 0;
+  // hops since the last refresh when every sample is known to have the same count
+  // (true from creation until a run-to-time call or a stall); -1 when unknown
+  int64_t lockstep_since = 0;
+};
+
+namespace {
+
+int fold_events(std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, double& acc) {
+  for (auto& e : ev) {
+    HIPCHK(hipEventSynchronize(e.second));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+    acc += ms;
+    HIPCHK(hipEventDestroy(e.first));
+    HIPCHK(hipEventDestroy(e.second));
+  }
+  ev.clear();
+  return CG_OK;
+}
+
+int ev_begin(cg_ctx* c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, double& acc,
+             hipEvent_t* start) {
+  if (ev.size() >= 1024) {
+    int rc = fold_events(ev, acc);
+    if (rc != CG_OK) return rc;
+  }
+  HIPCHK(hipEventCreate(start));
+  HIPCHK(hipEventRecord(*start, c->stream));
+  return CG_OK;
+}
+
+int ev_end(cg_ctx* c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, hipEvent_t start) {
+  hipEvent_t stop;
+  HIPCHK(hipEventCreate(&stop));
+  HIPCHK(hipEventRecord(stop, c->stream));
+  ev.emplace_back(start, stop);
+  return CG_OK;
+}
+
+int launch_hops(cg_ctx* c, int time_mode) {
+  const Plan& p = c->plan;
+  RunArgs ra;
+  ra.M = p.M;
+  ra.K = p.K;
+  ra.time_mode = time_mode;
+  ra.clock_mode = p.clock;
+  ra.max_labels = p.max_labels;
+  hipEvent_t start;
+  int rc = ev_begin(c, c->ev_hop, c->acc_hop_ms, &start);
+  if (rc != CG_OK) return rc;
+  const int32_t n = (int32_t)c->desc.size();
+  hipLaunchKernelGGL(c->hop, dim3(n), dim3(p.block), p.lds_hop, c->stream, c->d_samples, c->d_order, ra);
+  HIPCHK(hipGetLastError());
+  ++c->n_hop;
+  return ev_end(c, c->ev_hop, start);
+}
+
+int launch_exact(cg_ctx* c, int refresh) {
+  const Plan& p = c->plan;
+  const int32_t n = (int32_t)c->desc.size();
+  const dim3 grid((p.max_N + kInitBlock - 1) / kInitBlock, n);
+  hipEvent_t start;
+  if (refresh) {
+    int rc = ev_begin(c, c->ev_ref, c->acc_ref_ms, &start);
+    if (rc != CG_OK) return rc;
+  }
+  if (p.precision == CG_FP64)
+    hipLaunchKernelGGL(k_eps_exact<double>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
+                       refresh, p.K);
+  else
+    hipLaunchKernelGGL(k_eps_exact<float>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
+                       refresh, p.K);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(64), 0, c->stream, c->d_samples, refresh, p.K);
+  HIPCHK(hipGetLastError());
+  if (refresh) {
+    ++c->n_ref;
+    return ev_end(c, c->ev_ref, start);
+  }
+  return CG_OK;
+}
+
+int read_states(cg_ctx* c, std::vector<SampleState>& out) {
+  const int32_t n = (int32_t)c->desc.size();
+  out.resize(n);
+  for (int32_t b = 0; b < n; ++b)
+    HIPCHK(hipMemcpyAsync(&out[b], c->arena + c->plan.sl[b].st, sizeof(SampleState), hipMemcpyDeviceToHost,
+                          c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CG_OK;
+}
+
+int check_stall(cg_ctx* c) {
+  std::vector<SampleState> st;
+  int rc = read_states(c, st);
+  if (rc != CG_OK) return rc;
+  for (size_t b = 0; b < st.size(); ++b)
+    if (st[b].status != 0)
+      return set_err(CG_ESTALL, "sample %zu reached the label cap (%llu labels) before its target", b,
+                     (unsigned long long)c->plan.max_labels);
+  return CG_OK;
+}
+
+int sample_ok(cg_ctx* c, int32_t b) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  if (b < 0 || b >= (int32_t)c->desc.size()) return set_err(CG_EINVAL, "sample index %d out of range", b);
+  return CG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+const char* cg_last_error(void) { return g_err; }
+
+int cg_arena_bytes(const cg_sample_desc* samples, int32_t n, const cg_run_opts* opts, size_t* bytes) {
+  if (!bytes) return set_err(CG_EINVAL, "null output");
+  Plan p;
+  int rc = make_plan(samples, n, opts, p, false);
+  if (rc != CG_OK) return rc;
+  *bytes = p.total;
+  return CG_OK;
+}
+
+int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_run_opts* opts, void* arena,
+              size_t arena_bytes, void* hip_stream) {
+  if (!out) return set_err(CG_EINVAL, "null output");
+  *out = nullptr;
+  g_err[0] = 0;
+  Plan p;
+  int rc = make_plan(samples, n, opts, p, true);
+  if (rc != CG_OK) return rc;
+  if (!arena) return set_err(CG_EINVAL, "null arena");
+  if ((uintptr_t)arena % kAlign != 0) return set_err(CG_EINVAL, "arena must be %zu-byte aligned", kAlign);
+  if (arena_bytes < p.total) return set_err(CG_ENOSPC, "arena has %zu bytes, needs %zu", arena_bytes, p.total);
+
+  cg_ctx* c = new cg_ctx();
+  c->plan = p;
+  c->desc.assign(samples, samples + n);
+  c->arena = (uint8_t*)arena;
+  c->stream = (hipStream_t)hip_stream;
+  c->d_samples = (DevSample*)(c->arena + p.samples_off);
+  c->d_order = (int32_t*)(c->arena + p.order_off);
+  c->d_pending = (int32_t*)(c->arena + p.scratch_off);
+  c->hop = p.precision == CG_FP64 ? pick_hop<double>(p.U, p.layout) : pick_hop<float>(p.U, p.layout);
+
+  auto fail = [&](int code) {
+    delete c;
+    return code;
+  };
+  // host staging of every sample's static blocks (state, tables), then one copy each
+  std::vector<std::vector<uint8_t>> staging(n);
+  c->dev.resize(n);
+  for (int32_t b = 0; b < n; ++b) {
+    const cg_sample_desc& d = samples[b];
+    const SampleLayout& q = p.sl[b];
+    HostTables t;
+    rc = build_tables(d, p.layout, p.precision, t);
+    if (rc != CG_OK) return fail(rc);
+    const int32_t L = d.L, N = L * L;
+    const uint32_t magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)L - 1) / (uint64_t)L);
+    for (int32_t i = 0; i < N; ++i)
+      if ((int32_t)(((uint64_t)i * magic) >> 32) != i / L)
+        return fail(set_err(CG_EINVAL, "internal: row division check failed for L=%d", L));
+    std::vector<uint8_t>& sb = staging[b];
+    sb.assign(q.static_end - q.st, 0);
+    uint8_t* base = sb.data() - q.st;
+    std::memcpy(base + q.tab64, t.tab64.data(), t.tab64.size() * 8);
+    if (p.precision == CG_FP64)
+      std::memcpy(base + q.tabk, t.tabk64.data(), t.tabk64.size() * 8);
+    else
+      std::memcpy(base + q.tabk, t.tabk32.data(), t.tabk32.size() * 4);
+    std::memcpy(base + q.thr, t.thr.data(), t.thr.size() * 4);
+    std::memcpy(base + q.orb, t.orb.data(), t.orb.size() * 4);
+    std::memcpy(base + q.vec, t.vec.data(), t.vec.size() * 4);
+    std::memcpy(base + q.guide, t.guide.data(), t.guide.size());
+
+    DevSample& s = c->dev[b];
+    std::memset(&s, 0, sizeof(s));
+    s.L = L;
+    s.N = N;
+    s.H = t.H;
+    s.n_e = d.n_electrons;
+    s.NW = (N + 31) / 32;
+    s.n_orb = t.n_orb;
+    s.n_vec = t.n_vec;
+    s.ntab = p.layout == kTri ? tri_entries(t.H) : full_entries(t.H);
+    s.nblk = (N + kInitBlock - 1) / kInitBlock;
+    s.log_cap = p.log_cap;
+    s.layout = p.layout;
+    s.seed_lo = (uint32_t)d.seed;
+    s.seed_hi = (uint32_t)(d.seed >> 32);
+    s.sample_id = d.sample_id;
+    s.magic_L = magic;
+    s.nu = (double)d.n_electrons / (double)N;
+    s.W = d.W;
+    s.T = d.T;
+    s.E = d.E;
+    s.Gamma = t.Gamma;
+    s.T32 = (float)d.T;
+    s.E32 = (float)d.E;
+    s.invT32 = (float)(1.0 / d.T);
+    uint8_t* a = c->arena;
+    s.st = (SampleState*)(a + q.st);
+    s.eps = a + q.eps;
+    s.phi = (double*)(a + q.phi);
+    s.occ = (uint32_t*)(a + q.occ);
+    s.tab64 = (const double*)(a + q.tab64);
+    s.tabk = a + q.tabk;
+    s.thr = (const uint32_t*)(a + q.thr);
+    s.orb = (const uint32_t*)(a + q.orb);
+    s.vec = (const int32_t*)(a + q.vec);
+    s.guide = a + q.guide;
+    s.part = (double*)(a + q.part);
+    s.log_label = (uint64_t*)(a + q.log_label);
+    s.log_from = (int32_t*)(a + q.log_from);
+    s.log_to = (int32_t*)(a + q.log_to);
+  }
+#define HIPCHK_C(expr)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(set_err(CG_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                          __LINE__));                                                      \
+  } while (0)
+  for (int32_t b = 0; b < n; ++b)
+    HIPCHK_C(hipMemcpyAsync(c->arena + p.sl[b].st, staging[b].data(), staging[b].size(), hipMemcpyHostToDevice,
+                            c->stream));
+  HIPCHK_C(hipMemcpyAsync(c->d_samples, c->dev.data(), sizeof(DevSample) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK_C(hipMemcpyAsync(c->d_order, p.order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+
+  HIPCHK_C(hipFuncSetAttribute((const void*)c->hop, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop));
+  if (p.precision == CG_FP64)
+    HIPCHK_C(hipFuncSetAttribute((const void*)k_eps_exact<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 p.lds_exact));
+  else
+    HIPCHK_C(hipFuncSetAttribute((const void*)k_eps_exact<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 p.lds_exact));
+
+  // random initial state and FP64 energies, all on the device
+  const dim3 grid((p.max_N + kInitBlock - 1) / kInitBlock, n);
+  hipLaunchKernelGGL(k_init_keys, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
+  HIPCHK_C(hipGetLastError());
+  hipLaunchKernelGGL(k_init_rank, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
+  HIPCHK_C(hipGetLastError());
+  hipLaunchKernelGGL(k_init_phi, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
+  HIPCHK_C(hipGetLastError());
+  rc = launch_exact(c, 0);
+  if (rc != CG_OK) return fail(rc);
+  HIPCHK_C(hipStreamSynchronize(c->stream));
+#undef HIPCHK_C
+  *out = c;
+  return CG_OK;
+}
+
+int cg_destroy(cg_ctx* c) {
+  if (!c) return CG_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev_hop) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& e : c->ev_ref) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete c;
+  return CG_OK;
+}
+
+int cg_run_hops(cg_ctx* c, int64_t n_hops) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  if (n_hops < 1) return set_err(CG_EINVAL, "n_hops=%lld must be >= 1", (long long)n_hops);
+  const int32_t n = (int32_t)c->desc.size();
+  hipLaunchKernelGGL(k_begin_call, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->d_samples, n, n_hops, -1.0, 0);
+  HIPCHK(hipGetLastError());
+  int rc;
+  if (c->plan.precision == CG_FP64) {
+    rc = launch_hops(c, 0);
+    if (rc != CG_OK) return rc;
+  } else if (c->lockstep_since >= 0) {
+    // every sample has the same hops-since-refresh: launch exactly one hop kernel per
+    // refresh interval and a refresh where an interval completes
+    const int64_t K = c->plan.K;
+    int64_t left = n_hops, since = c->lockstep_since;
+    while (left > 0) {
+      const int64_t k = std::min(left, K - since);
+      rc = launch_hops(c, 0);
+      if (rc != CG_OK) return rc;
+      left -= k;
+      since += k;
+      if (since == K) {
+        rc = launch_exact(c, 1);
+        if (rc != CG_OK) return rc;
+        since = 0;
+      }
+    }
+    c->lockstep_since = since;
+  } else {
+    // unknown per-sample counts: at most ceil(n/K) + 1 launches; finished samples exit at once
+    const int64_t K = c->plan.K;
+    const int64_t rounds = (n_hops + K - 1) / K + 1;
+    for (int64_t r = 0; r < rounds; ++r) {
+      rc = launch_hops(c, 0);
+      if (rc != CG_OK) return rc;
+      rc = launch_exact(c, 1);
+      if (rc != CG_OK) return rc;
+    }
+  }
+  rc = check_stall(c);
+  if (rc == CG_ESTALL) c->lockstep_since = -1;
+  return rc;
+}
+
+int cg_run_time(cg_ctx* c, double t_end) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  if (!(t_end >= 0.0) || !std::isfinite(t_end)) return set_err(CG_EINVAL, "t_end=%g", t_end);
+  const int32_t n = (int32_t)c->desc.size();
+  hipLaunchKernelGGL(k_begin_call, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->d_samples, n, (int64_t)0,
+                     t_end, 1);
+  HIPCHK(hipGetLastError());
+  c->lockstep_since = -1;
+  for (;;) {
+    int rc = launch_hops(c, 1);
+    if (rc != CG_OK) return rc;
+    if (c->plan.precision != CG_FP64) {
+      rc = launch_exact(c, 1);
+      if (rc != CG_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_pending, dim3(1), dim3(256), 0, c->stream, c->d_samples, n, c->d_pending);
+    HIPCHK(hipGetLastError());
+    int32_t pending = 0;
+    HIPCHK(hipMemcpyAsync(&pending, c->d_pending, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (pending == 0) break;
+  }
+  return check_stall(c);
+}
+
+int cg_refresh(cg_ctx* c) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  const int32_t n = (int32_t)c->desc.size();
+  hipLaunchKernelGGL(k_force_refresh, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->d_samples, n);
+  HIPCHK(hipGetLastError());
+  int rc = launch_exact(c, 1);
+  if (rc != CG_OK) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->lockstep_since >= 0) c->lockstep_since = 0;
+  return CG_OK;
+}
+
+int cg_set_TE(cg_ctx* c, int32_t b, double T, double E) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!(T > 0.0) || !std::isfinite(T) || !std::isfinite(E)) return set_err(CG_EINVAL, "T=%g E=%g", T, E);
+  c->desc[b].T = T;
+  c->desc[b].E = E;
+  DevSample& s = c->dev[b];
+  s.T = T;
+  s.E = E;
+  s.T32 = (float)T;
+  s.E32 = (float)E;
+  s.invT32 = (float)(1.0 / T);
+  HIPCHK(hipMemcpyAsync(c->d_samples + b, &s, sizeof(DevSample), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CG_OK;
+}
+
+int cg_get_occupation(cg_ctx* c, int32_t b, uint8_t* host_out) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!host_out) return set_err(CG_EINVAL, "null output");
+  const DevSample& s = c->dev[b];
+  std::vector<uint32_t> w(s.NW);
+  HIPCHK(hipMemcpyAsync(w.data(), s.occ, 4 * (size_t)s.NW, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int32_t l = 0; l < s.N; ++l) host_out[l] = (uint8_t)((w[l >> 5] >> (l & 31)) & 1u);
+  return CG_OK;
+}
+
+int cg_get_local_energies(cg_ctx* c, int32_t b, double* host_out) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!host_out) return set_err(CG_EINVAL, "null output");
+  const DevSample& s = c->dev[b];
+  if (c->plan.precision == CG_FP64) {
+    HIPCHK(hipMemcpyAsync(host_out, s.eps, 8 * (size_t)s.N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<float> f(s.N);
+    HIPCHK(hipMemcpyAsync(f.data(), s.eps, 4 * (size_t)s.N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int32_t l = 0; l < s.N; ++l) host_out[l] = (double)f[l];
+  }
+  return CG_OK;
+}
+
+int cg_get_phi(cg_ctx* c, int32_t b, double* host_out) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!host_out) return set_err(CG_EINVAL, "null output");
+  const DevSample& s = c->dev[b];
+  HIPCHK(hipMemcpyAsync(host_out, s.phi, 8 * (size_t)s.N, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return CG_OK;
+}
+
+int cg_get_stats(cg_ctx* c, int32_t b, cg_stats* out) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!out) return set_err(CG_EINVAL, "null output");
+  SampleState st;
+  HIPCHK(hipMemcpyAsync(&st, c->dev[b].st, sizeof(st), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  out->hops = st.hops;
+  out->s_last = st.s_last;
+  out->s_scan = st.s_scan;
+  out->P = st.P;
+  out->t = st.t;
+  out->H0 = st.H0;
+  out->sum_p = st.sum_p;
+  out->rounds = st.rounds;
+  out->evaluated = st.evaluated;
+  out->theta_pass = st.theta_pass;
+  out->refreshes = st.refreshes;
+  out->max_drift = st.max_drift;
+  out->last_drift = st.last_drift;
+  out->status = st.status;
+  out->since_refresh = st.since_refresh;
+  out->logged = st.logged;
+  return CG_OK;
+}
+
+int cg_get_current(cg_ctx* c, int32_t b, double* t, int64_t* P, double* sigma) {
+  cg_stats s;
+  int rc = cg_get_stats(c, b, &s);
+  if (rc != CG_OK) return rc;
+  const double N = (double)c->dev[b].N, E = c->desc[b].E;
+  if (t) *t = s.t;
+  if (P) *P = s.P;
+  if (sigma) *sigma = (E * s.t != 0.0) ? (double)s.P / (N * E * s.t) : 0.0;
+  return CG_OK;
+}
+
+int cg_get_hop_log(cg_ctx* c, int32_t b, uint64_t* labels, int32_t* from, int32_t* to, int64_t cap,
+                   int64_t* count) {
+  cg_stats s;
+  int rc = cg_get_stats(c, b, &s);
+  if (rc != CG_OK) return rc;
+  if (cap < 0 || !count) return set_err(CG_EINVAL, "bad log arguments");
+  const int64_t k = std::min<int64_t>(cap, s.logged);
+  const DevSample& d = c->dev[b];
+  if (k > 0) {
+    if (!labels || !from || !to) return set_err(CG_EINVAL, "null log output");
+    HIPCHK(hipMemcpyAsync(labels, d.log_label, 8 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(from, d.log_from, 4 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(to, d.log_to, 4 * (size_t)k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  *count = k;
+  return CG_OK;
+}
+
+int cg_take_kernel_time(cg_ctx* c, double* hop_ms, int64_t* hop_launches, double* refresh_ms,
+                        int64_t* refresh_launches) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  int rc = fold_events(c->ev_hop, c->acc_hop_ms);
+  if (rc != CG_OK) return rc;
+  rc = fold_events(c->ev_ref, c->acc_ref_ms);
+  if (rc != CG_OK) return rc;
+  if (hop_ms) *hop_ms = c->acc_hop_ms;
+  if (hop_launches) *hop_launches = c->n_hop;
+  if (refresh_ms) *refresh_ms = c->acc_ref_ms;
+  if (refresh_launches) *refresh_launches = c->n_ref;
+  c->acc_hop_ms = c->acc_ref_ms = 0.0;
+  c->n_hop = c->n_ref = 0;
+  return CG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// layout.hpp -- data structures shared by the host side and the kernels of libcgkmc.
+//
+// Per sample, the arena holds (each block 256-byte aligned):
+//   SampleState                          counters, clock, energy totals, run targets
+//   eps   [N]    float | double          local energies (the form's precision)
+//   phi   [N]    double                  disorder (scratch for init keys before that)
+//   occ   [NW]   u32                     occupation bits, site l -> word l>>5, bit l&31
+//   tab64 [(H+1)^2] double               1/r by folded separation (|dy|, |dx|), H = L/2
+//   tabk  [ntab] float | double          the hop kernel's 1/r table (full or triangular)
+//   thr   [n_orb] u32                    cumulative orbit thresholds (last one unused)
+//   orb   [n_orb] u32                    first member | (orbit size - 1) << 16
+//   vec   [n_vec] i32                    member displacement (dx & 0xffff) | dy << 16
+//   guide [1024] u8                      orbit at the start of each 2^22-wide bucket of w1
+//   part  [2 * nblk] double              per-block partial sums (energy, drift)
+//   log   [cap] u64 + 2 x [cap] i32      executed-hop log (label, from, to)
+#pragma once
+
+#include <stdint.h>
+
+namespace cg {
+
+constexpr int kGuideBits = 10;
+constexpr int kGuideSize = 1 << kGuideBits;
+constexpr int kMaxWaves = 16;       // 1024 threads of 64 lanes
+constexpr int kMaxCols = 4;         // columns per lane in the row update: L <= 256
+constexpr int kInitBlock = 256;     // threads per block of the init / refresh kernels
+
+enum TableLayout : int32_t { kFull = 0, kTri = 1 };
+
+struct SampleState {
+  uint64_t s_last;        // label of the last executed hop
+  uint64_t s_scan;        // all labels <= s_scan decided
+  uint64_t hops;          // executed hops
+  uint64_t hop_target;    // stop when hops reaches this (per call)
+  uint64_t call_scan0;    // s_scan at the start of the current call
+  int64_t P;              // sum of executed dx
+  double t;               // clock
+  double H0;              // field-free energy
+  double t_end;           // run-to-time target of the current call (< 0: none)
+  uint64_t sum_p;         // sum of ceil(m / M)
+  uint64_t rounds;        // evaluation rounds
+  uint64_t evaluated;     // label evaluations
+  uint64_t theta_pass;    // evaluations passing the occupancy filter
+  uint64_t refreshes;     // FP64 refreshes done
+  double max_drift;       // max over refreshes of max |eps32 - eps64|
+  double last_drift;
+  int64_t logged;         // hop-log entries written (capped at the capacity)
+  int32_t status;         // 0 ok, CG_ESTALL
+  int32_t since_refresh;  // hops since last refresh
+  int32_t force_refresh;  // refresh kernel: refresh regardless of since_refresh
+  int32_t pad_;
+};
+
+struct DevSample {
+  int32_t L, N, H, n_e;
+  int32_t NW, n_orb, n_vec, ntab;   // ntab: entries of the hop kernel's table
+  int32_t nblk, log_cap, layout, pad_;
+  uint32_t seed_lo, seed_hi, sample_id, magic_L;  // magic_L = ceil(2^32 / L)
+  double nu, W, T, E, Gamma;
+  float T32, E32, invT32, pad32_;
+  SampleState* st;
+  void* eps;
+  double* phi;
+  uint32_t* occ;
+  const double* tab64;
+  const void* tabk;
+  const uint32_t* thr;
+  const uint32_t* orb;
+  const int32_t* vec;
+  const uint8_t* guide;
+  double* part;
+  uint64_t* log_label;
+  int32_t* log_from;
+  int32_t* log_to;
+};
+
+// Knobs of one hop-kernel launch (uniform over the batch).
+struct RunArgs {
+  int32_t M;            // labels per parallel iteration = block * labels_per_lane
+  int32_t K;            // FP32 form: stop a sample when since_refresh reaches K (0: never)
+  int32_t time_mode;    // 1: stop after the hop that brings t >= t_end
+  int32_t clock_mode;   // 0: t = s_last / Gamma ; 1: Gaussian increments
+  uint64_t max_labels;  // per-call label cap (stall guard)
+};
+
+__host__ __device__ inline int32_t align16(int32_t b) { return (b + 15) & ~15; }
+
+// Dynamic LDS layout of the hop kernel (byte offsets); identical on host and device.
+struct HopLds {
+  int32_t eps, occ, tab, vec, thr, orb, guide, ctrl, info, total;
+};
+
+constexpr int32_t kInfoBytes = 32;
+
+__host__ __device__ inline HopLds hop_lds(int32_t N, int32_t NW, int32_t ntab, int32_t n_vec,
+                                          int32_t n_orb, int32_t real_bytes) {
+  HopLds o;
+  int32_t b = 0;
+  o.eps = b;   b = align16(b + N * real_bytes);
+  o.occ = b;   b = align16(b + NW * 4);
+  o.tab = b;   b = align16(b + ntab * real_bytes);
+  o.vec = b;   b = align16(b + n_vec * 4);
+  o.thr = b;   b = align16(b + n_orb * 4);
+  o.orb = b;   b = align16(b + n_orb * 4);
+  o.guide = b; b = align16(b + kGuideSize);
+  o.ctrl = b;  b = align16(b + 96);
+  o.info = b;  b = align16(b + kMaxWaves * kInfoBytes);
+  o.total = b;
+  return o;
+}
+
+__host__ __device__ inline int32_t tri_entries(int32_t H) { return (H + 1) * (H + 2) / 2; }
+__host__ __device__ inline int32_t full_entries(int32_t H) { return (H + 1) * (H + 1); }
+
+}  // namespace cg
