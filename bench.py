@@ -27,6 +27,29 @@ sys.path.insert(0, ROOT)
 
 # 256 CUs x 128 B/clk x 2.4 GHz: LDS bandwidth of the chip (see the measurement notes)
 LDS_PEAK_GBS = 256 * 128 * 2.4
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hops_l128_batch256_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1407_5026_amd", "csrc", "kernels.hpp")
+
+
+def kernel_hash() -> str:
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per hop-kernel launch from the committed counter runs (FETCH_SIZE and
+    WRITE_SIZE scaled by a copy kernel of known size), or None when the kernel source has
+    changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def _cpu_worker(args):
@@ -89,13 +112,16 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--hops-per-step", type=int, default=4096)
-    ap.add_argument("--M", type=int, default=2048)
+    ap.add_argument("--M", type=int, default=1024)
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--cpu-hops", type=int, default=3000)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before timing, copy this many MiB with a plain device copy (a counter "
+                         "calibration point for FETCH_SIZE / WRITE_SIZE runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (samples are independent; a batch would split across "
@@ -109,6 +135,14 @@ def main() -> int:
 
     cg.load()
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {n} bytes done", file=sys.stderr, flush=True)
+        del src, dst
     samples = headline(args.batch)
     N = samples[0].L ** 2
     print(f"[bench] FP32+refresh: B={args.batch} L=128 hops/step={args.hops_per_step} "
@@ -155,7 +189,7 @@ def main() -> int:
         "fp32_max_drift": r32["max_drift"],
         "refresh_ms_per_step": r32["refresh_ms"] / args.steps,
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_hops<float>", "bytes_per_hop": bytes_per_hop,
                      "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
     }

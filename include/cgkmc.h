@@ -46,13 +46,13 @@ extern "C" {
 #define CG_ESTALL (-4)   /* label cap reached before the requested hops; state is valid */
 
 #define CG_FP64 0          /* proposals, acceptance and energy update in FP64            */
-#define CG_FP32_REFRESH 1  /* FP32 proposals/update, FP64 O(N^2) refresh every K hops    */
+#define CG_FP32_REFRESH 1  /* FP32 proposals/update (Kahan-compensated), FP64 refresh every K hops */
 
 #define CG_CLOCK_DET 0    /* dt = m / Gamma (deterministic increment)                    */
 #define CG_CLOCK_GAUSS 1  /* dt ~ Gaussian(m/Gamma, sqrt(m)/Gamma), clamped at 0 (step 3c) */
 
 /* One independent sample (disorder realisation / temperature / size).
- * Requirements: 3 <= L, L*L <= 65536; 1 <= n_electrons < L*L; W >= 0; xi > 0;
+ * Requirements: 3 <= L <= 192; 1 <= n_electrons < L*L; W >= 0; xi > 0;
  * 1 <= rc < L/2 (hops longer than L/2 are excluded, section "Results ... two
  * dimensions"); T > 0. */
 typedef struct cg_sample_desc {
@@ -70,11 +70,18 @@ typedef struct cg_sample_desc {
 
 typedef struct cg_run_opts {
   int32_t precision;   /* CG_FP64 or CG_FP32_REFRESH                                    */
-  int32_t M;           /* labels per parallel iteration: block * {1,2,4,8}; 0 = block   */
-  int32_t block;       /* threads per workgroup: 256, 512 or 1024; 0 = 1024              */
+  int32_t M;           /* parallel width of one PR iteration (power of two; 0 = 1024): the
+                          iteration count p = ceil(m / M) is reported per hop; the kernel
+                          evaluates labels in chunks of 1024 (M <= 1024) or 2048 and the
+                          executed hops do not depend on M                               */
+  int32_t block;       /* threads per workgroup: 1024 (0 = 1024)                         */
   int32_t K_refresh;   /* FP32 form: hops between FP64 refreshes (>= 1); 0 = 4096       */
   int32_t clock_mode;  /* CG_CLOCK_DET or CG_CLOCK_GAUSS                                 */
   int32_t log_hops;    /* per-sample capacity of the executed-hop log (0 = no log)       */
+  int32_t phase_timers;/* 1: accumulate per-phase shader cycles into cg_stats            */
+  int32_t use_graph;   /* 1: cg_run_hops captures its launch sequence once per (n_hops,
+                          refresh phase) as a hipGraph and replays it; needs a stream
+                          other than the legacy default stream                          */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;
 
@@ -96,6 +103,9 @@ typedef struct cg_stats {
   int32_t status;       /* CG_OK, or CG_ESTALL if the label cap stopped this sample     */
   int32_t since_refresh;/* hops since the last refresh (FP32 form)                      */
   int64_t logged;       /* entries written to the hop log                              */
+  uint64_t phase_cycles[4]; /* with phase_timers: shader cycles in label drawing,
+                               evaluation + lowest-label reduction, hop execution, and the
+                               energy update (each including its barrier)              */
 } cg_stats;
 
 typedef struct cg_ctx cg_ctx;
@@ -127,7 +137,8 @@ int cg_refresh(cg_ctx* ctx);
 int cg_set_TE(cg_ctx* ctx, int32_t sample, double T, double E);
 
 /* Host copies: occupation (N bytes), local energies as FP64 (N doubles; the FP32 form
- * widens), disorder phi (N doubles), counters. */
+ * returns its value word plus the compensated low part), disorder phi (N doubles),
+ * counters. */
 int cg_get_occupation(cg_ctx* ctx, int32_t sample, uint8_t* host_out);
 int cg_get_local_energies(cg_ctx* ctx, int32_t sample, double* host_out);
 int cg_get_phi(cg_ctx* ctx, int32_t sample, double* host_out);
@@ -139,10 +150,20 @@ int cg_get_current(cg_ctx* ctx, int32_t sample, double* t, int64_t* P, double* s
 int cg_get_hop_log(cg_ctx* ctx, int32_t sample, uint64_t* labels, int32_t* from, int32_t* to,
                    int64_t cap, int64_t* count);
 
-/* Device time of the hop kernel launches since the last call (ms) and launch count;
- * resets both.  Timing uses HIP events on the context stream. */
+/* Device time of the hop kernel launches since the last call (ms) and launch count, and
+ * the same for refreshes; resets them.  Timing uses HIP events on the context stream; with
+ * use_graph, each replay is timed as a whole and added to the hop time. */
 int cg_take_kernel_time(cg_ctx* ctx, double* hop_ms, int64_t* hop_launches, double* refresh_ms,
                         int64_t* refresh_launches);
+
+/* Autotuner: chooses opts->M (the kernel's label chunk, 1024 or 2048) by the hop-kernel
+ * time of trial runs of trial_hops hops, and, in the FP32 form, opts->K_refresh as the
+ * largest of 8192, 4096, 2048, 1024 whose drift over 2K hops from the initial state stays
+ * below drift_target / 2 (else 1024).  Each trial creates and destroys a context on
+ * `arena` (at least cg_arena_bytes for these samples and options), whose contents are
+ * overwritten; no context is left behind.  Runs on hip_stream and synchronises it. */
+int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, void* arena,
+                size_t arena_bytes, void* hip_stream, int64_t trial_hops, double drift_target);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* cg_last_error(void);

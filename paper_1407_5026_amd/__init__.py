@@ -31,7 +31,7 @@ CG_CLOCK_GAUSS = 1
 EXPORTS = (
     "cg_arena_bytes", "cg_create", "cg_destroy", "cg_run_hops", "cg_run_time", "cg_refresh",
     "cg_set_TE", "cg_get_occupation", "cg_get_local_energies", "cg_get_phi", "cg_get_stats",
-    "cg_get_current", "cg_get_hop_log", "cg_take_kernel_time", "cg_last_error",
+    "cg_get_current", "cg_get_hop_log", "cg_take_kernel_time", "cg_autotune", "cg_last_error",
 )
 
 
@@ -44,7 +44,7 @@ class cg_sample_desc(C.Structure):
 class cg_run_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("M", C.c_int32), ("block", C.c_int32),
                 ("K_refresh", C.c_int32), ("clock_mode", C.c_int32), ("log_hops", C.c_int32),
-                ("max_labels_per_call", C.c_uint64)]
+                ("phase_timers", C.c_int32), ("use_graph", C.c_int32), ("max_labels_per_call", C.c_uint64)]
 
 
 class cg_stats(C.Structure):
@@ -52,7 +52,8 @@ class cg_stats(C.Structure):
                 ("t", C.c_double), ("H0", C.c_double), ("sum_p", C.c_uint64), ("rounds", C.c_uint64),
                 ("evaluated", C.c_uint64), ("theta_pass", C.c_uint64), ("refreshes", C.c_uint64),
                 ("max_drift", C.c_double), ("last_drift", C.c_double), ("status", C.c_int32),
-                ("since_refresh", C.c_int32), ("logged", C.c_int64)]
+                ("since_refresh", C.c_int32), ("logged", C.c_int64),
+                ("phase_cycles", C.c_uint64 * 4)]
 
 
 class CgError(RuntimeError):
@@ -94,6 +95,8 @@ def load(path: str = LIB_PATH):
     L.cg_get_hop_log.argtypes = [vp, C.c_int32, P(C.c_uint64), P(C.c_int32), P(C.c_int32), C.c_int64,
                                  P(C.c_int64)]
     L.cg_take_kernel_time.argtypes = [vp, P(C.c_double), P(C.c_int64), P(C.c_double), P(C.c_int64)]
+    L.cg_autotune.argtypes = [P(cg_sample_desc), C.c_int32, P(cg_run_opts), vp, C.c_size_t, vp, C.c_int64,
+                              C.c_double]
     L.cg_last_error.restype = C.c_char_p
     for f in EXPORTS:
         if f != "cg_last_error":
@@ -118,8 +121,9 @@ def _descs(samples):
 
 
 def make_opts(precision=CG_FP64, M=0, block=0, K_refresh=0, clock_mode=CG_CLOCK_DET, log_hops=0,
-              max_labels_per_call=0) -> cg_run_opts:
-    return cg_run_opts(precision, M, block, K_refresh, clock_mode, log_hops, max_labels_per_call)
+              max_labels_per_call=0, phase_timers=0, use_graph=0) -> cg_run_opts:
+    return cg_run_opts(precision, M, block, K_refresh, clock_mode, log_hops, phase_timers, use_graph,
+                       max_labels_per_call)
 
 
 def arena_bytes(samples, opts: cg_run_opts) -> int:
@@ -127,6 +131,25 @@ def arena_bytes(samples, opts: cg_run_opts) -> int:
     n = C.c_size_t()
     _check(load().cg_arena_bytes(d, len(samples), C.byref(opts), C.byref(n)))
     return n.value
+
+
+def autotune(samples, opts: cg_run_opts, trial_hops: int = 2048, drift_target: float = 1e-5,
+             device="cuda") -> cg_run_opts:
+    """Tuned copy of `opts` (chunk width M and, in the FP32 form, refresh period K) from short
+    trial runs of these samples in a scratch arena."""
+    import torch
+
+    lib = load()
+    d = _descs(samples)
+    nbytes = arena_bytes(samples, opts)
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (arena.data_ptr() + 255) & ~255
+    out = cg_run_opts.from_buffer_copy(opts)
+    stream = torch.cuda.current_stream(arena.device)
+    _check(lib.cg_autotune(d, len(samples), C.byref(out), C.c_void_p(ptr), nbytes,
+                           C.c_void_p(stream.cuda_stream), int(trial_hops), float(drift_target)))
+    del arena
+    return out
 
 
 class Batch:
@@ -144,7 +167,11 @@ class Batch:
         self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         ptr = self.arena.data_ptr()
         self._arena_ptr = (ptr + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.arena.device)
+        if stream is None:
+            # graph replay cannot capture the legacy default stream: give the batch its own
+            stream = (torch.cuda.Stream(self.arena.device) if self.opts.use_graph
+                      else torch.cuda.current_stream(self.arena.device))
+        self.stream = stream
         self.N = [int(d.L) * int(d.L) for d in self._descs]
         h = C.c_void_p()
         _check(lib.cg_create(C.byref(h), self._descs, self.n, C.byref(self.opts),
@@ -194,7 +221,9 @@ class Batch:
     def stats(self, b: int) -> dict:
         s = cg_stats()
         _check(load().cg_get_stats(self._h, b, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in cg_stats._fields_}
+        d = {k: getattr(s, k) for k, _ in cg_stats._fields_}
+        d["phase_cycles"] = list(s.phase_cycles)
+        return d
 
     def current(self, b: int):
         t, P, sig = C.c_double(), C.c_int64(), C.c_double()

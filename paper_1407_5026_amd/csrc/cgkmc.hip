@@ -58,6 +58,8 @@ struct HostTables {
   std::vector<double> tab64;  // full folded table
   std::vector<double> tabk64;
   std::vector<float> tabk32;
+  std::vector<double> dft_tw;  // [L][2]
+  std::vector<double> dft_T;   // [H+1][L]
   double wsum = 0.0, Gamma = 0.0;
 };
 
@@ -149,6 +151,25 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
     t.tabk32.resize(nk);
     for (size_t k = 0; k < nk; ++k) t.tabk32[k] = (float)k64[k];
   }
+  // refresh tables: twiddles (cos, sin)(2 pi j / L) and the x-transform of 1/r,
+  // That(k, dy) = sum_dx T(fold dx, fold dy) cos(2 pi k dx / L) -- real because T is even in dx
+  const double two_pi = 6.283185307179586;
+  t.dft_tw.resize((size_t)2 * L);
+  for (int32_t jj = 0; jj < L; ++jj) {
+    t.dft_tw[2 * jj] = std::cos(two_pi * (double)jj / (double)L);
+    t.dft_tw[2 * jj + 1] = std::sin(two_pi * (double)jj / (double)L);
+  }
+  t.dft_T.assign((size_t)H1 * L, 0.0);
+  for (int32_t k = 0; k < H1; ++k)
+    for (int32_t dy = 0; dy < L; ++dy) {
+      const int32_t ay = std::min(dy, L - dy);
+      double acc2 = 0.0;
+      for (int32_t dx = 0; dx < L; ++dx) {
+        const int32_t ax = std::min(dx, L - dx);
+        acc2 += t.tab64[(size_t)ay * H1 + ax] * t.dft_tw[2 * (size_t)(((int64_t)k * dx) % L)];
+      }
+      t.dft_T[(size_t)k * L + dy] = acc2;
+    }
   return CG_OK;
 }
 
@@ -172,15 +193,18 @@ int32_t count_vectors(double rc) {
 
 // ---------------------------------------------------------------------------------
 struct SampleLayout {
-  size_t st, tab64, tabk, thr, orb, vec, guide, static_end;  // uploaded in one copy
+  size_t tab64, tabk, thr, orb, vec, guide, dft_tw, dft_T, static_end;  // uploaded in one copy
   size_t eps, phi, occ, part, log_label, log_from, log_to, end;
+  int32_t dft, dft_kc, dft_rows;
 };
 
 struct Plan {
-  int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0;
-  int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, max_N = 0;
+  int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0, timers = 0;
+  int32_t use_graph = 0;
+  int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
+  bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
   uint64_t max_labels = 1ull << 32;
-  size_t samples_off = 0, order_off = 0, scratch_off = 0, total = 0;
+  size_t states_off = 0, samples_off = 0, order_off = 0, scratch_off = 0, total = 0;
   std::vector<SampleLayout> sl;
   std::vector<int32_t> order;
 };
@@ -197,7 +221,7 @@ int max_lds_bytes(int32_t* out) {
 
 int validate(const cg_sample_desc& d, int32_t b) {
   const int32_t L = d.L;
-  if (L < 3 || L > 256 || L * L > 65536) return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 256]", b, L);
+  if (L < 3 || L > 192) return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 192]", b, L);
   const int32_t N = L * L;
   if (d.n_electrons < 1 || d.n_electrons >= N)
     return set_err(CG_EINVAL, "sample %d: n_electrons=%d outside [1, N-1]", b, d.n_electrons);
@@ -218,13 +242,17 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (p.precision != CG_FP64 && p.precision != CG_FP32_REFRESH)
     return set_err(CG_EINVAL, "precision=%d", o->precision);
   p.block = o->block ? o->block : 1024;
-  if (p.block != 256 && p.block != 512 && p.block != 1024)
-    return set_err(CG_EINVAL, "block=%d (256, 512 or 1024)", o->block);
-  p.M = o->M ? o->M : p.block;
-  if (p.M % p.block != 0) return set_err(CG_EINVAL, "M=%d is not a multiple of block=%d", o->M, p.block);
-  p.U = p.M / p.block;
-  if (p.U != 1 && p.U != 2 && p.U != 4 && p.U != 8)
-    return set_err(CG_EINVAL, "M/block=%d (1, 2, 4 or 8 labels per lane)", p.U);
+  if (p.block != 1024) return set_err(CG_EINVAL, "block=%d (the hop kernel runs 1024 threads per sample)", o->block);
+  // M: the paper's parallel width, used for the iteration count p = ceil(m / M); the kernel
+  // evaluates labels in chunks of 1024 U (the executed hops do not depend on either)
+  p.M = o->M ? o->M : 1024;
+  if (p.M < 1 || (p.M & (p.M - 1)) != 0 || p.M > (1 << 20))
+    return set_err(CG_EINVAL, "M=%d must be a power of two in [1, 2^20]", o->M);
+  p.U = p.M > 1024 ? 2 : 1;
+  if (o->phase_timers != 0 && o->phase_timers != 1) return set_err(CG_EINVAL, "phase_timers=%d", o->phase_timers);
+  p.timers = o->phase_timers;
+  if (o->use_graph != 0 && o->use_graph != 1) return set_err(CG_EINVAL, "use_graph=%d", o->use_graph);
+  p.use_graph = o->use_graph;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
   if (p.precision == CG_FP64) p.K = 0;
@@ -242,14 +270,19 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   }
   // table layout: full (|dy|,|dx|) table if every sample fits, else the triangle
   bool full_fits = true, tri_fits = true;
+  int32_t max_L_all = 0;
+  for (int32_t b = 0; b < n; ++b) max_L_all = std::max(max_L_all, s[b].L);
   int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
   for (int32_t b = 0; b < n; ++b) {
     int rc = validate(s[b], b);
     if (rc != CG_OK) return rc;
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
-    const int32_t f = hop_lds(N, NW, full_entries(H), n_vec, n_orb, p.real_bytes).total;
-    const int32_t t = hop_lds(N, NW, tri_entries(H), n_vec, n_orb, p.real_bytes).total;
+    // energy bytes in LDS: FP32 value words (registers hold the pairs), FP64 values in place,
+    // none when the batch's largest lattice exceeds 128 (energies stay in the arena)
+    const int32_t eb = max_L_all > 128 ? 0 : p.real_bytes;
+    const int32_t f = hop_lds(N, NW, full_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
+    const int32_t t = hop_lds(N, NW, tri_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
     need_full = std::max(need_full, f);
     need_tri = std::max(need_tri, t);
     full_fits = full_fits && f <= lds_cap;
@@ -260,12 +293,12 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (full_fits) {
     p.layout = kFull;
     p.lds_hop = need_full;
-  } else if (tri_fits) {
+  } else if (tri_fits && p.precision == CG_FP64) {
     p.layout = kTri;
     p.lds_hop = need_tri;
   } else {
     return set_err(CG_ENOSPC, "a sample needs %d bytes of LDS for its energies and tables (%d available)",
-                   need_tri, lds_cap);
+                   p.precision == CG_FP64 ? need_tri : need_full, lds_cap);
   }
   if (need_exact + 2 * kInitBlock * 8 > lds_cap)
     return set_err(CG_ENOSPC, "refresh kernel needs %d bytes of LDS", need_exact);
@@ -274,13 +307,28 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
 
   size_t off = 0;
   p.sl.resize(n);
+  p.states_off = off;
+  off = align_up(off + sizeof(SampleState) * (size_t)n);
+  int32_t max_L = 0;
   for (int32_t b = 0; b < n; ++b) {
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
     const int32_t ntab = p.layout == kTri ? tri_entries(H) : full_entries(H);
     const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
+    max_L = std::max(max_L, L);
     SampleLayout& q = p.sl[b];
-    q.st = off;        off = align_up(off + sizeof(SampleState));
+    // refresh by Fourier transform when every thread's outputs fit its registers and a
+    // frequency chunk fits LDS; otherwise the O(N^2) exact-order kernel refreshes it
+    const int32_t G = 1024 / L;
+    const int32_t fixed = align16(NW * 4) + L * 16 + 512;
+    int32_t kc = std::min<int32_t>(H + 1, (lds_cap - fixed) / (24 * L));
+    kc = std::min<int32_t>(kc, kDftItems * 1024 / L);
+    q.dft = (G >= 1 && (L + G - 1) / G <= kDftRowsMax && kc >= 1) ? 1 : 0;
+    q.dft_rows = G >= 1 ? (L + G - 1) / G : 0;
+    if (q.dft) (q.dft_rows > 16 ? p.dft32 : p.dft16) = true;
+    q.dft_kc = q.dft ? kc : 0;
+    if (q.dft) p.lds_dft = std::max(p.lds_dft, fixed + kc * L * 24);
+    else p.any_exact_refresh = true;
     q.tab64 = off;     off = align_up(off + (size_t)full_entries(H) * 8);
     q.tabk = off;      off = align_up(off + (size_t)full_entries(H) * p.real_bytes);
     (void)ntab;
@@ -288,8 +336,10 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.orb = off;       off = align_up(off + (size_t)n_orb * 4);
     q.vec = off;       off = align_up(off + (size_t)n_vec * 4);
     q.guide = off;     off = align_up(off + kGuideSize);
+    q.dft_tw = off;    off = align_up(off + (size_t)L * 16);
+    q.dft_T = off;     off = align_up(off + (size_t)(H + 1) * L * 8);
     q.static_end = off;
-    q.eps = off;       off = align_up(off + (size_t)N * p.real_bytes);
+    q.eps = off;       off = align_up(off + (size_t)N * 8);  // double, or FP32 value + low part
     q.phi = off;       off = align_up(off + (size_t)N * 8);
     q.occ = off;       off = align_up(off + (size_t)NW * 4);
     q.part = off;      off = align_up(off + (size_t)2 * nblk * 8);
@@ -298,6 +348,9 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
     q.end = off;
   }
+  p.NC = max_L <= 64 ? 1 : (max_L <= 128 ? 2 : 3);
+  p.exact = true;
+  for (int32_t b = 0; b < n; ++b) p.exact = p.exact && s[b].L == 64 * p.NC;
   p.samples_off = off; off = align_up(off + sizeof(DevSample) * (size_t)n);
   p.order_off = off;   off = align_up(off + sizeof(int32_t) * (size_t)n);
   p.scratch_off = off; off = align_up(off + 64);
@@ -313,15 +366,26 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
 
 using HopFn = void (*)(const DevSample*, const int32_t*, RunArgs);
 
-template <typename R>
-HopFn pick_hop(int32_t U, int32_t layout) {
-  const bool tri = layout == kTri;
-  switch (U) {
-    case 1: return tri ? k_hops<R, 1, true> : k_hops<R, 1, false>;
-    case 2: return tri ? k_hops<R, 2, true> : k_hops<R, 2, false>;
-    case 4: return tri ? k_hops<R, 4, true> : k_hops<R, 4, false>;
-    default: return tri ? k_hops<R, 8, true> : k_hops<R, 8, false>;
+// Kernel geometry from the largest lattice: NC column blocks of 64 and RPW rows per wave;
+// "exact" when every sample fills it (L = 64 NC = 16 RPW), which removes all bounds checks.
+// Energy storage: FP32 registers + LDS values, FP64 in LDS, both in the arena beyond L = 128.
+template <typename R, int U, bool TRI, int MODE>
+HopFn pick_geo(int32_t NC, bool exact) {
+  if (NC == 1) return exact ? k_hops<R, U, TRI, 1, 4, true, MODE> : k_hops<R, U, TRI, 1, 4, false, MODE>;
+  return exact ? k_hops<R, U, TRI, 2, 8, true, MODE> : k_hops<R, U, TRI, 2, 8, false, MODE>;
+}
+
+HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact) {
+  if (NC >= 3) {  // L > 128: energies in the arena
+    if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
+    return k_hops<float, 1, false, 3, 12, false, kModeGlobal>;
   }
+  if (precision == CG_FP64) {
+    if (layout == kTri)
+      return U == 1 ? pick_geo<double, 1, true, kModeLds>(NC, exact) : pick_geo<double, 2, true, kModeLds>(NC, exact);
+    return U == 1 ? pick_geo<double, 1, false, kModeLds>(NC, exact) : pick_geo<double, 2, false, kModeLds>(NC, exact);
+  }
+  return U == 1 ? pick_geo<float, 1, false, kModeReg>(NC, exact) : pick_geo<float, 2, false, kModeReg>(NC, exact);
 }
 
 }  // namespace
@@ -343,6 +407,17 @@ struct cg_ctx {
   // hops since the last refresh when every sample is known to have the same count
   // (true from creation until a run-to-time call or a stall); -1 when unknown
   int64_t lockstep_since = 0;
+  // captured launch sequences of cg_run_hops, keyed by (n_hops, lockstep_since)
+  struct Graph {
+    int64_t n_hops, since0, since1;
+    int32_t hop_launches, ref_launches;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+  bool capturing = false;
+  double acc_graph_ms = 0.0;
+  int64_t n_graph = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_graph;
 };
 
 namespace {
@@ -380,12 +455,33 @@ int ev_end(cg_ctx* c, std::vector<std::pair<hipEvent_t, hipEvent_t>>& ev, hipEve
 }
 
 int launch_hops(cg_ctx* c, int time_mode) {
+  if (c->capturing) {
+    const Plan& p = c->plan;
+    RunArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.M = p.M;
+    while ((1 << ra.log2M) < p.M) ++ra.log2M;
+    ra.K = p.K;
+    ra.time_mode = time_mode;
+    ra.clock_mode = p.clock;
+    ra.timers = p.timers;
+    ra.max_labels = p.max_labels;
+    hipLaunchKernelGGL(c->hop, dim3((int32_t)c->desc.size()), dim3(p.block), p.lds_hop, c->stream, c->d_samples,
+                       c->d_order, ra);
+    HIPCHK(hipGetLastError());
+    ++c->n_hop;
+    return CG_OK;
+  }
   const Plan& p = c->plan;
   RunArgs ra;
+  std::memset(&ra, 0, sizeof(ra));
   ra.M = p.M;
+  ra.log2M = 0;
+  while ((1 << ra.log2M) < p.M) ++ra.log2M;
   ra.K = p.K;
   ra.time_mode = time_mode;
   ra.clock_mode = p.clock;
+  ra.timers = p.timers;
   ra.max_labels = p.max_labels;
   hipEvent_t start;
   int rc = ev_begin(c, c->ev_hop, c->acc_hop_ms, &start);
@@ -401,33 +497,43 @@ int launch_exact(cg_ctx* c, int refresh) {
   const Plan& p = c->plan;
   const int32_t n = (int32_t)c->desc.size();
   const dim3 grid((p.max_N + kInitBlock - 1) / kInitBlock, n);
-  hipEvent_t start;
+  hipEvent_t start = nullptr;
+  const bool timed = refresh && !c->capturing;
   if (refresh) {
-    int rc = ev_begin(c, c->ev_ref, c->acc_ref_ms, &start);
-    if (rc != CG_OK) return rc;
+    if (timed) {
+      int rc = ev_begin(c, c->ev_ref, c->acc_ref_ms, &start);
+      if (rc != CG_OK) return rc;
+    }
+    if (p.precision != CG_FP64 && p.dft16) {
+      hipLaunchKernelGGL((k_refresh_dft<float, 16>), dim3(n), dim3(1024), p.lds_dft, c->stream, c->d_samples, p.K);
+      HIPCHK(hipGetLastError());
+    }
+    if (p.precision != CG_FP64 && p.dft32) {
+      hipLaunchKernelGGL((k_refresh_dft<float, 32>), dim3(n), dim3(1024), p.lds_dft, c->stream, c->d_samples, p.K);
+      HIPCHK(hipGetLastError());
+    }
   }
-  if (p.precision == CG_FP64)
-    hipLaunchKernelGGL(k_eps_exact<double>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
-                       refresh, p.K);
-  else
-    hipLaunchKernelGGL(k_eps_exact<float>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
-                       refresh, p.K);
-  HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(64), 0, c->stream, c->d_samples, refresh, p.K);
-  HIPCHK(hipGetLastError());
-  if (refresh) {
-    ++c->n_ref;
-    return ev_end(c, c->ev_ref, start);
+  if (!refresh || p.any_exact_refresh || p.precision == CG_FP64) {
+    if (p.precision == CG_FP64)
+      hipLaunchKernelGGL(k_eps_exact<double>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
+                         refresh, p.K);
+    else
+      hipLaunchKernelGGL(k_eps_exact<float>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
+                         refresh, p.K);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(64), 0, c->stream, c->d_samples, refresh, p.K);
+    HIPCHK(hipGetLastError());
   }
+  if (refresh) ++c->n_ref;
+  if (timed) return ev_end(c, c->ev_ref, start);
   return CG_OK;
 }
 
 int read_states(cg_ctx* c, std::vector<SampleState>& out) {
   const int32_t n = (int32_t)c->desc.size();
   out.resize(n);
-  for (int32_t b = 0; b < n; ++b)
-    HIPCHK(hipMemcpyAsync(&out[b], c->arena + c->plan.sl[b].st, sizeof(SampleState), hipMemcpyDeviceToHost,
-                          c->stream));
+  HIPCHK(hipMemcpyAsync(out.data(), c->arena + c->plan.states_off, sizeof(SampleState) * n, hipMemcpyDeviceToHost,
+                        c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return CG_OK;
 }
@@ -485,7 +591,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   c->d_samples = (DevSample*)(c->arena + p.samples_off);
   c->d_order = (int32_t*)(c->arena + p.order_off);
   c->d_pending = (int32_t*)(c->arena + p.scratch_off);
-  c->hop = p.precision == CG_FP64 ? pick_hop<double>(p.U, p.layout) : pick_hop<float>(p.U, p.layout);
+  c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact);
 
   auto fail = [&](int code) {
     delete c;
@@ -506,8 +612,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
       if ((int32_t)(((uint64_t)i * magic) >> 32) != i / L)
         return fail(set_err(CG_EINVAL, "internal: row division check failed for L=%d", L));
     std::vector<uint8_t>& sb = staging[b];
-    sb.assign(q.static_end - q.st, 0);
-    uint8_t* base = sb.data() - q.st;
+    sb.assign(q.static_end - q.tab64, 0);
+    uint8_t* base = sb.data() - q.tab64;
     std::memcpy(base + q.tab64, t.tab64.data(), t.tab64.size() * 8);
     if (p.precision == CG_FP64)
       std::memcpy(base + q.tabk, t.tabk64.data(), t.tabk64.size() * 8);
@@ -517,6 +623,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     std::memcpy(base + q.orb, t.orb.data(), t.orb.size() * 4);
     std::memcpy(base + q.vec, t.vec.data(), t.vec.size() * 4);
     std::memcpy(base + q.guide, t.guide.data(), t.guide.size());
+    std::memcpy(base + q.dft_tw, t.dft_tw.data(), t.dft_tw.size() * 8);
+    std::memcpy(base + q.dft_T, t.dft_T.data(), t.dft_T.size() * 8);
 
     DevSample& s = c->dev[b];
     std::memset(&s, 0, sizeof(s));
@@ -531,6 +639,9 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.nblk = (N + kInitBlock - 1) / kInitBlock;
     s.log_cap = p.log_cap;
     s.layout = p.layout;
+    s.dft = q.dft;
+    s.dft_kc = q.dft_kc;
+    s.dft_rows = q.dft_rows;
     s.seed_lo = (uint32_t)d.seed;
     s.seed_hi = (uint32_t)(d.seed >> 32);
     s.sample_id = d.sample_id;
@@ -544,7 +655,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.E32 = (float)d.E;
     s.invT32 = (float)(1.0 / d.T);
     uint8_t* a = c->arena;
-    s.st = (SampleState*)(a + q.st);
+    s.st = (SampleState*)(a + p.states_off) + b;
     s.eps = a + q.eps;
     s.phi = (double*)(a + q.phi);
     s.occ = (uint32_t*)(a + q.occ);
@@ -555,6 +666,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.vec = (const int32_t*)(a + q.vec);
     s.guide = a + q.guide;
     s.part = (double*)(a + q.part);
+    s.dft_tw = (const double*)(a + q.dft_tw);
+    s.dft_T = (const double*)(a + q.dft_T);
     s.log_label = (uint64_t*)(a + q.log_label);
     s.log_from = (int32_t*)(a + q.log_from);
     s.log_to = (int32_t*)(a + q.log_to);
@@ -567,18 +680,32 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
                           __LINE__));                                                      \
   } while (0)
   for (int32_t b = 0; b < n; ++b)
-    HIPCHK_C(hipMemcpyAsync(c->arena + p.sl[b].st, staging[b].data(), staging[b].size(), hipMemcpyHostToDevice,
+    HIPCHK_C(hipMemcpyAsync(c->arena + p.sl[b].tab64, staging[b].data(), staging[b].size(), hipMemcpyHostToDevice,
                             c->stream));
+  {
+    std::vector<SampleState> zero(n);
+    std::memset(zero.data(), 0, sizeof(SampleState) * n);
+    HIPCHK_C(hipMemcpyAsync(c->arena + p.states_off, zero.data(), sizeof(SampleState) * n, hipMemcpyHostToDevice,
+                            c->stream));
+    HIPCHK_C(hipStreamSynchronize(c->stream));
+  }
   HIPCHK_C(hipMemcpyAsync(c->d_samples, c->dev.data(), sizeof(DevSample) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK_C(hipMemcpyAsync(c->d_order, p.order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
 
   HIPCHK_C(hipFuncSetAttribute((const void*)c->hop, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop));
-  if (p.precision == CG_FP64)
+  if (p.precision == CG_FP64) {
     HIPCHK_C(hipFuncSetAttribute((const void*)k_eps_exact<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  p.lds_exact));
-  else
+  } else {
     HIPCHK_C(hipFuncSetAttribute((const void*)k_eps_exact<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  p.lds_exact));
+    if (p.lds_dft > 0) {
+      HIPCHK_C(hipFuncSetAttribute((const void*)k_refresh_dft<float, 16>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_dft));
+      HIPCHK_C(hipFuncSetAttribute((const void*)k_refresh_dft<float, 32>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_dft));
+    }
+  }
 
   // random initial state and FP64 energies, all on the device
   const dim3 grid((p.max_N + kInitBlock - 1) / kInitBlock, n);
@@ -607,13 +734,19 @@ int cg_destroy(cg_ctx* c) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  for (auto& e : c->ev_graph) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
   delete c;
   return CG_OK;
 }
 
-int cg_run_hops(cg_ctx* c, int64_t n_hops) {
-  if (!c) return set_err(CG_EINVAL, "null context");
-  if (n_hops < 1) return set_err(CG_EINVAL, "n_hops=%lld must be >= 1", (long long)n_hops);
+namespace {
+
+// Enqueue the launch sequence of run_hops(n_hops) (no synchronisation, no host reads).
+int enqueue_run_hops(cg_ctx* c, int64_t n_hops) {
   const int32_t n = (int32_t)c->desc.size();
   hipLaunchKernelGGL(k_begin_call, dim3((n + 255) / 256), dim3(256), 0, c->stream, c->d_samples, n, n_hops, -1.0, 0);
   HIPCHK(hipGetLastError());
@@ -649,6 +782,66 @@ int cg_run_hops(cg_ctx* c, int64_t n_hops) {
       rc = launch_exact(c, 1);
       if (rc != CG_OK) return rc;
     }
+  }
+  return CG_OK;
+}
+
+}  // namespace
+
+int cg_run_hops(cg_ctx* c, int64_t n_hops) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  if (n_hops < 1) return set_err(CG_EINVAL, "n_hops=%lld must be >= 1", (long long)n_hops);
+  int rc;
+  const bool graph = c->plan.use_graph && (c->plan.precision == CG_FP64 || c->lockstep_since >= 0);
+  if (!graph) {
+    rc = enqueue_run_hops(c, n_hops);
+    if (rc != CG_OK) return rc;
+  } else {
+    // replay the captured launch sequence of this (n_hops, refresh phase); capture on first use
+    const int64_t since0 = c->lockstep_since;
+    cg_ctx::Graph* g = nullptr;
+    for (auto& e : c->graphs)
+      if (e.n_hops == n_hops && e.since0 == since0) g = &e;
+    if (!g) {
+      cg_ctx::Graph e;
+      e.n_hops = n_hops;
+      e.since0 = since0;
+      const int64_t h0 = c->n_hop, r0 = c->n_ref;
+      HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      c->capturing = true;
+      rc = enqueue_run_hops(c, n_hops);
+      c->capturing = false;
+      hipGraph_t graph_ = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->stream, &graph_);
+      if (rc != CG_OK) {
+        if (graph_) (void)hipGraphDestroy(graph_);
+        return rc;
+      }
+      if (ec != hipSuccess)
+        return set_err(CG_EHIP, "stream capture failed (%s); graph replay needs a non-default stream",
+                       hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&e.exec, graph_, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph_);
+      HIPCHK(ei);
+      e.since1 = c->lockstep_since;
+      e.hop_launches = (int32_t)(c->n_hop - h0);
+      e.ref_launches = (int32_t)(c->n_ref - r0);
+      c->n_hop = h0;
+      c->n_ref = r0;
+      c->lockstep_since = since0;
+      c->graphs.push_back(e);
+      g = &c->graphs.back();
+    }
+    hipEvent_t start;
+    rc = ev_begin(c, c->ev_graph, c->acc_graph_ms, &start);
+    if (rc != CG_OK) return rc;
+    HIPCHK(hipGraphLaunch(g->exec, c->stream));
+    rc = ev_end(c, c->ev_graph, start);
+    if (rc != CG_OK) return rc;
+    ++c->n_graph;
+    c->n_hop += g->hop_launches;
+    c->n_ref += g->ref_launches;
+    c->lockstep_since = g->since1;
   }
   rc = check_stall(c);
   if (rc == CG_ESTALL) c->lockstep_since = -1;
@@ -730,10 +923,11 @@ int cg_get_local_energies(cg_ctx* c, int32_t b, double* host_out) {
     HIPCHK(hipMemcpyAsync(host_out, s.eps, 8 * (size_t)s.N, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   } else {
-    std::vector<float> f(s.N);
-    HIPCHK(hipMemcpyAsync(f.data(), s.eps, 4 * (size_t)s.N, hipMemcpyDeviceToHost, c->stream));
+    // FP32 form: value word plus its compensated low part
+    std::vector<float> f(2 * (size_t)s.N);
+    HIPCHK(hipMemcpyAsync(f.data(), s.eps, 8 * (size_t)s.N, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    for (int32_t l = 0; l < s.N; ++l) host_out[l] = (double)f[l];
+    for (int32_t l = 0; l < s.N; ++l) host_out[l] = (double)f[2 * l] + (double)f[2 * l + 1];
   }
   return CG_OK;
 }
@@ -771,6 +965,7 @@ int cg_get_stats(cg_ctx* c, int32_t b, cg_stats* out) {
   out->status = st.status;
   out->since_refresh = st.since_refresh;
   out->logged = st.logged;
+  for (int k = 0; k < 4; ++k) out->phase_cycles[k] = st.phase_cycles[k];
   return CG_OK;
 }
 
@@ -804,6 +999,66 @@ int cg_get_hop_log(cg_ctx* c, int32_t b, uint64_t* labels, int32_t* from, int32_
   return CG_OK;
 }
 
+int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, void* arena, size_t arena_bytes,
+                void* hip_stream, int64_t trial_hops, double drift_target) {
+  if (!opts) return set_err(CG_EINVAL, "null options");
+  if (trial_hops < 64) return set_err(CG_EINVAL, "trial_hops=%lld must be >= 64", (long long)trial_hops);
+  if (!(drift_target > 0.0)) return set_err(CG_EINVAL, "drift_target=%g", drift_target);
+  // 1) chunk width: the candidate with the least hop-kernel time over trial_hops hops
+  const int32_t Ms[2] = {1024, 2048};
+  double best_ms = 0.0;
+  int32_t best_M = Ms[0];
+  for (int32_t M : Ms) {
+    cg_run_opts o = *opts;
+    o.M = M;
+    o.log_hops = 0;
+    o.phase_timers = 0;
+    o.use_graph = 0;
+    if (o.precision != CG_FP64) o.K_refresh = 1 << 20;  // no refresh inside the timing trial
+    cg_ctx* c = nullptr;
+    int rc = cg_create(&c, samples, n, &o, arena, arena_bytes, hip_stream);
+    if (rc != CG_OK) return rc;
+    rc = cg_run_hops(c, trial_hops / 2);
+    double ms = 0.0;
+    if (rc == CG_OK) rc = cg_take_kernel_time(c, nullptr, nullptr, nullptr, nullptr);
+    if (rc == CG_OK) rc = cg_run_hops(c, trial_hops);
+    if (rc == CG_OK) rc = cg_take_kernel_time(c, &ms, nullptr, nullptr, nullptr);
+    cg_destroy(c);
+    if (rc != CG_OK) return rc;
+    if (M == Ms[0] || ms < best_ms) {
+      best_ms = ms;
+      best_M = M;
+    }
+  }
+  opts->M = best_M;
+  if (opts->precision == CG_FP64) return CG_OK;
+  // 2) refresh period: the largest K whose drift over 2K hops from the initial state, where
+  //    the energies are widest, stays below half the target
+  const int32_t Ks[4] = {8192, 4096, 2048, 1024};
+  for (int32_t K : Ks) {
+    cg_run_opts o = *opts;
+    o.K_refresh = K;
+    o.log_hops = 0;
+    o.phase_timers = 0;
+    o.use_graph = 0;
+    cg_ctx* c = nullptr;
+    int rc = cg_create(&c, samples, n, &o, arena, arena_bytes, hip_stream);
+    if (rc != CG_OK) return rc;
+    rc = cg_run_hops(c, 2 * (int64_t)K);
+    double worst = 0.0;
+    for (int32_t b = 0; b < n && rc == CG_OK; ++b) {
+      cg_stats st;
+      rc = cg_get_stats(c, b, &st);
+      worst = std::max(worst, st.max_drift);
+    }
+    cg_destroy(c);
+    if (rc != CG_OK) return rc;
+    opts->K_refresh = K;
+    if (worst <= 0.5 * drift_target) return CG_OK;
+  }
+  return CG_OK;
+}
+
 int cg_take_kernel_time(cg_ctx* c, double* hop_ms, int64_t* hop_launches, double* refresh_ms,
                         int64_t* refresh_launches) {
   if (!c) return set_err(CG_EINVAL, "null context");
@@ -811,6 +1066,12 @@ int cg_take_kernel_time(cg_ctx* c, double* hop_ms, int64_t* hop_launches, double
   if (rc != CG_OK) return rc;
   rc = fold_events(c->ev_ref, c->acc_ref_ms);
   if (rc != CG_OK) return rc;
+  rc = fold_events(c->ev_graph, c->acc_graph_ms);
+  if (rc != CG_OK) return rc;
+  // graph replays are timed as a whole and counted with the hop launches they contain
+  c->acc_hop_ms += c->acc_graph_ms;
+  c->acc_graph_ms = 0.0;
+  c->n_graph = 0;
   if (hop_ms) *hop_ms = c->acc_hop_ms;
   if (hop_launches) *hop_launches = c->n_hop;
   if (refresh_ms) *refresh_ms = c->acc_ref_ms;

@@ -71,6 +71,16 @@ __device__ __forceinline__ bool metropolis(double dH, double u, const DevSample&
 __device__ __forceinline__ bool metropolis(float dH, float u, const DevSample& S) {
   return dH <= 0.0f || u < __expf(-dH * S.invT32);
 }
+// Branch-free forms for the evaluation round.  FP32: the exponential is evaluated on every
+// lane (v_exp_f32); FP64: only lanes that passed the occupancy filter with dH > 0 call exp.
+__device__ __forceinline__ bool metropolis_nb(float dH, float u, bool, const DevSample& S) {
+  return (dH <= 0.0f) | (u < __expf(-dH * S.invT32));
+}
+__device__ __forceinline__ bool metropolis_nb(double dH, double u, bool th, const DevSample& S) {
+  bool a = dH <= 0.0;
+  if (th && !a) a = u < exp(-dH / S.T);
+  return a;
+}
 __device__ __forceinline__ double field(const DevSample& S, double) { return S.E; }
 __device__ __forceinline__ float field(const DevSample& S, float) { return S.E32; }
 
@@ -93,6 +103,16 @@ __device__ __forceinline__ int tidx(int ady, int adx, int H1) {
 
 __device__ __forceinline__ int row_of(int i, uint32_t magic) { return (int)__umulhi((uint32_t)i, magic); }
 
+// Values equal on every lane, moved to scalar registers so that the compiler treats
+// branches on them as uniform.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | (uint64_t)uni((uint32_t)v);
+}
+__device__ __forceinline__ int64_t uni(int64_t v) { return (int64_t)uni((uint64_t)v); }
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(v))); }
+
 struct HopInfo {
   uint32_t key;  // position of the label in the chunk: tid * U + k
   int32_t i, j, v;
@@ -101,66 +121,118 @@ struct HopInfo {
 };
 static_assert(sizeof(HopInfo) == kInfoBytes, "HopInfo size");
 
-// Step 3b on the LDS-resident energies: eps_l += 1/r_lj - 1/r_li for every l.  Lane
-// handles columns lane + 64 c (outer loop), wave w rows w, w + nw, ... (inner loop), so the
-// folded column separations are per-lane constants of the inner loop and the folded row
-// separations are wave-uniform.
-template <typename R, bool TRI>
-__device__ __forceinline__ void update_energies(R* __restrict__ eps, const R* __restrict__ tab,
-                                                int i, int j, int L, int H1, uint32_t magic,
-                                                int lane, int wid, int nw) {
-  const int yi = row_of(i, magic), xi = i - yi * L;
-  const int yj = row_of(j, magic), xj = j - yj * L;
-  for (int x0 = 0; x0 < L; x0 += 64) {
-    const int x = x0 + lane;
-    if (x < L) {
-      const int axi = fold(x - xi, L), axj = fold(x - xj, L);
-      for (int y = wid; y < L; y += nw) {
-        const int ayi = fold(y - yi, L), ayj = fold(y - yj, L);
-        const R tj = tab[tidx<TRI>(ayj, axj, H1)];
-        const R ti = tab[tidx<TRI>(ayi, axi, H1)];
-        R* __restrict__ e = eps + y * L + x;
-        *e = *e + (tj - ti);
-      }
-    }
+// Storage of one local energy.  FP64 form: the FP64 value, updated as e + (t_j - t_i)
+// exactly like the definition.  FP32 form: an FP32 pair (value, low part) updated by
+// Kahan's compensated summation, so that the pair tracks the exact running sum of the FP32
+// increments and the value word -- the FP32 energy every proposal reads -- stays within
+// about one rounding of it between refreshes.
+template <typename R> struct Energy;
+template <> struct Energy<double> {
+  using T = double;
+  __device__ static double value(T e) { return e; }
+  __device__ static T add(T e, double d) { return e + d; }
+  __device__ static T from64(double v) { return v; }
+};
+template <> struct Energy<float> {
+  using T = float2;
+  __device__ static float value(T e) { return e.x; }
+  __device__ static T add(T e, float d) {
+    const float y = d + e.y;
+    const float t = e.x + y;
+    return make_float2(t, y - (t - e.x));
   }
-}
-
-// Per-sample scalars in LDS: written by thread 0 only, read by all after a barrier.
-struct HopShared {
-  uint32_t wmask[3];   // per-round bitmask of waves holding an accepted label
-  uint32_t theta;      // theta-pass count (summed at exit)
-  double t;            // clock after the last executed hop
-  int64_t P;
-  double H0;
-  uint64_t sum_p, rounds, evaluated;
-  int64_t logged;
+  __device__ static T from64(double v) {
+    const float h = (float)v;
+    return make_float2(h, (float)(v - (double)h));
+  }
 };
 
-template <typename R, int U, bool TRI>
+template <bool TRI>
+__device__ __forceinline__ int tri_of(int a) { return (a * (a + 1)) >> 1; }
+
+// Gaussian clock increment of step 3c for hop number h with m serial proposals:
+// Box-Muller on the CLOCK stream, mean m/Gamma, deviation sqrt(m)/Gamma, clamped at 0.
+__device__ __noinline__ double gauss_dt(uint64_t h, uint64_t m, uint32_t sid, uint32_t k0, uint32_t k1,
+                                        double Gamma) {
+  uint32_t c0 = (uint32_t)h, c1 = (uint32_t)(h >> 32), c2 = sid, c3 = kTagClock;
+  philox10(c0, c1, c2, c3, k0, k1);
+  const double u1 = unit52(c0, c1), u2 = unit52(c2, c3);
+  const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  const double mean = (double)m / Gamma;
+  const double sd = sqrt((double)m) / Gamma;
+  const double dt = mean + sd * z;
+  return dt < 0.0 ? 0.0 : dt;
+}
+
+// Smallest label s with s / Gamma >= t_end (the deterministic clock is s_last / Gamma).
+__device__ __noinline__ uint64_t label_at_time(double t_end, double Gamma) {
+  double g = ceil(t_end * Gamma);
+  uint64_t s = g > 0.0 ? (uint64_t)g : 0;
+  while (s > 0 && (double)(s - 1) / Gamma >= t_end) --s;
+  while ((double)s / Gamma < t_end) ++s;
+  return s;
+}
+
+// Workgroup-shared control words: per-round bitmask of waves holding an accepted label
+// (triple-buffered, see the round loop), the clock of the Gaussian mode, theta count.
+struct HopShared {
+  uint64_t best[3];  // per-round minimum of (label key << 32 | i << 16 | j), triple-buffered
+  uint32_t theta;
+  uint32_t pad_;
+  double t;
+  double dummy;  // sink for the stores of lanes beyond the lattice
+};
+
+// The persistent hop kernel.  Threads own sites: wave w (16 waves) owns rows w + 16 r,
+// r < RPW, and lane the columns lane + 64 c, c < NC; the owned energies live in registers
+// (FP64, or the compensated FP32 pair) and their value words are mirrored in LDS for the
+// proposals.  Step 3b then costs, per site and hop, two LDS reads of the 1/r table, one
+// register update and one LDS write; the row separations of a wave are scalar.
+// Where the energies live during a launch.
+enum EnergyMode : int {
+  kModeReg = 0,     // owned energies in registers, value words mirrored in LDS
+  kModeLds = 1,     // energies in LDS, updated in place (FP64: value = storage)
+  kModeGlobal = 2,  // energies in the arena (HBM/L2), updated in place; for lattices whose
+                    // energies do not fit LDS
+};
+
+template <typename R, int U, bool TRI, int NC, int RPW, bool EXACT, int MODE>
 __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ samples,
                                                const int32_t* __restrict__ order, RunArgs ra) {
+  constexpr int NW = 16;
+  using ET = typename Energy<R>::T;
   const DevSample& S = samples[order[blockIdx.x]];
   SampleState* __restrict__ gs = S.st;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int lane = tid & 63, wid = tid >> 6, nw = nthr >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+  uint64_t hops = uni(gs->hops);
+  uint64_t s_last = uni(gs->s_last);
+  uint64_t done = uni(gs->s_scan);
+  int32_t since = uni(gs->since_refresh);
+  const uint64_t target = uni(gs->hop_target);
+  const uint64_t scan0 = uni(gs->call_scan0);
+  const double t_end = uni(gs->t_end);
+  const double t_start = uni(gs->t);
   {
-    const bool idle = gs->status != 0 || gs->hops >= gs->hop_target ||
-                      (ra.time_mode && gs->t >= gs->t_end) || (ra.K > 0 && gs->since_refresh >= ra.K);
+    const bool idle = uni(gs->status) != 0 || hops >= target || (ra.time_mode && t_start >= t_end) ||
+                      (ra.K > 0 && since >= ra.K);
     if (idle) return;
   }
-  uint64_t hops = gs->hops;
-  uint64_t s_last = gs->s_last;
-  uint64_t done = gs->s_scan;
-  int32_t since = gs->since_refresh;
+  int64_t P = uni(gs->P);
+  double H0 = uni(gs->H0);
+  uint64_t sum_p = uni(gs->sum_p), rounds = uni(gs->rounds), evaluated = uni(gs->evaluated);
+  int64_t logged = uni(gs->logged);
   int32_t status = 0;
 
   const int L = S.L, N = S.N, H1 = S.H + 1, n_orb = S.n_orb;
   const uint32_t magic = S.magic_L;
   extern __shared__ __align__(16) uint8_t smem[];
-  const HopLds lo = hop_lds(N, S.NW, S.ntab, S.n_vec, n_orb, (int32_t)sizeof(R));
-  R* __restrict__ eps = (R*)(smem + lo.eps);
+  const int32_t eb = MODE == kModeReg ? (int32_t)sizeof(R) : (MODE == kModeLds ? (int32_t)sizeof(ET) : 0);
+  const HopLds lo = hop_lds(N, S.NW, S.ntab, S.n_vec, n_orb, eb, (int32_t)sizeof(R));
+  R* __restrict__ ev = (R*)(smem + lo.eps);  // kModeReg: value words of all energies
+  ET* __restrict__ es = MODE == kModeLds ? (ET*)(smem + lo.eps) : (ET*)S.eps;  // in-place storage
   uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
   R* __restrict__ tab = (R*)(smem + lo.tab);
   int32_t* __restrict__ vec = (int32_t*)(smem + lo.vec);
@@ -170,43 +242,69 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
   HopShared* __restrict__ sh = (HopShared*)(smem + lo.ctrl);
   HopInfo* __restrict__ info = (HopInfo*)(smem + lo.info);
 
+  // owned energies: registers mirrored in LDS, or in-place LDS storage, or the arena
+  ET E[MODE == kModeReg ? RPW : 1][MODE == kModeReg ? NC : 1];
   {
-    const R* g = (const R*)S.eps;
-    for (int k = tid; k < N; k += nthr) eps[k] = g[k];
+    const ET* __restrict__ g = (const ET*)S.eps;
+    if constexpr (MODE == kModeReg) {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int y = wid + NW * r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int x = lane + 64 * c;
+          if (y < L && x < L) {
+            E[r][c] = g[y * L + x];
+            ev[y * L + x] = Energy<R>::value(E[r][c]);
+          } else {
+            E[r][c] = ET();
+          }
+        }
+      }
+    } else if constexpr (MODE == kModeLds) {
+      for (int k = tid; k < N; k += 1024) es[k] = g[k];
+    }
     const R* gt = (const R*)S.tabk;
-    for (int k = tid; k < S.ntab; k += nthr) tab[k] = gt[k];
+    for (int k = tid; k < S.ntab; k += 1024) tab[k] = gt[k];
   }
-  for (int k = tid; k < S.NW; k += nthr) occ[k] = S.occ[k];
-  for (int k = tid; k < S.n_vec; k += nthr) vec[k] = S.vec[k];
-  for (int k = tid; k < n_orb; k += nthr) {
+  for (int k = tid; k < S.NW; k += 1024) occ[k] = S.occ[k];
+  for (int k = tid; k < S.n_vec; k += 1024) vec[k] = S.vec[k];
+  for (int k = tid; k < n_orb; k += 1024) {
     thr[k] = S.thr[k];
     orb[k] = S.orb[k];
   }
-  for (int k = tid; k < kGuideSize; k += nthr) guide[k] = S.guide[k];
+  for (int k = tid; k < kGuideSize; k += 1024) guide[k] = S.guide[k];
   if (tid == 0) {
-    sh->wmask[0] = sh->wmask[1] = sh->wmask[2] = 0u;
+    sh->best[0] = sh->best[1] = sh->best[2] = ~0ull;
     sh->theta = 0u;
-    sh->t = gs->t;
-    sh->P = gs->P;
-    sh->H0 = gs->H0;
-    sh->sum_p = gs->sum_p;
-    sh->rounds = gs->rounds;
-    sh->evaluated = gs->evaluated;
-    sh->logged = gs->logged;
+    sh->t = t_start;
   }
   __syncthreads();
 
   const uint32_t k0 = S.seed_lo, k1 = S.seed_hi, sid = S.sample_id;
-  const uint64_t M = (uint64_t)ra.M;
+  const uint64_t M = (uint64_t)(1024 * U);
+  // deterministic clock in run-to-time mode: stop at the first hop with label >= s_end
+  const uint64_t s_end = uni((ra.time_mode && ra.clock_mode == 0) ? label_at_time(t_end, S.Gamma) : (uint64_t)0);
   const R Ef = field(S, R(0));
   uint64_t base = done;  // current chunk: labels base+1 .. base+M
   bool cached = false;
-  int ci[U], cj[U], cv[U];
+  int ci[U], cj[U], ct[U], cdx[U];
   R cu[U];
   uint32_t theta_cnt = 0;
   uint32_t it = 0;
+  // optional phase timers (shader clock): refill, evaluate + round barrier, execute, update + barrier
+  uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
+  const bool timers = ra.timers != 0;
+#define CG_MARK(acc)                                          \
+  if (timers) {                                               \
+    const uint64_t now_ = __builtin_amdgcn_s_memtime();       \
+    acc += now_ - tmark;                                      \
+    tmark = now_;                                             \
+  }
+  if (timers) tmark = __builtin_amdgcn_s_memtime();
 
   for (;;) {
+    // P: draw this lane's labels of the chunk once; they are re-used after a hop
     if (!cached) {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
@@ -228,39 +326,49 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         yj -= yj >= L ? L : 0;
         ci[k] = i;
         cj[k] = yj * L + xj;
-        cv[k] = v;
+        ct[k] = tidx<TRI>(dy < 0 ? -dy : dy, dx < 0 ? -dx : dx, H1);
+        cdx[k] = dx;
         cu[k] = accept_uniform<R>(c2, c3);
       }
       cached = true;
+      CG_MARK(tc0)
     }
 
-    // R: evaluate the undecided labels of this lane, keep the first accepted one
+    // R: evaluate the undecided labels of this lane, keep the first accepted one.  The two
+    // occupation words, both energies and 1/r are loaded unconditionally and combined
+    // without branches, so a round costs one LDS round trip.
     const uint64_t active = base + M - done;
-    int first = U, fi = 0, fj = 0, fv = 0;
+    int first = U, fi = 0, fj = 0, fdx = 0;
     double fdh0 = 0.0;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
-      if (first == U && lab > done) {
-        const int i = ci[k], j = cj[k];
-        const bool th = ((occ[i >> 5] >> (i & 31)) & 1u) && !((occ[j >> 5] >> (j & 31)) & 1u);
-        if (th) {
-          ++theta_cnt;
-          const int pv = vec[cv[k]];
-          const int dx = (int)(int16_t)(pv & 0xffff), dy = pv >> 16;
-          const R td = tab[tidx<TRI>(dy < 0 ? -dy : dy, dx < 0 ? -dx : dx, H1)];
-          const R dh0 = (eps[j] - eps[i]) - td;
-          const R dH = dh0 - Ef * (R)dx;
-          if (metropolis(dH, cu[k], S)) {
-            first = k;
-            fi = i;
-            fj = j;
-            fv = cv[k];
-            fdh0 = (double)dh0;
-          }
-        }
+      const int i = ci[k], j = cj[k];
+      const uint32_t wi = occ[i >> 5], wj = occ[j >> 5];
+      R ei, ej;
+      if constexpr (MODE == kModeReg) {
+        ei = ev[i];
+        ej = ev[j];
+      } else {
+        ei = Energy<R>::value(es[i]);
+        ej = Energy<R>::value(es[j]);
+      }
+      const R td = tab[ct[k]];
+      const bool th = (first == U) & (lab > done) & ((((wi >> (i & 31)) & ~(wj >> (j & 31))) & 1u) != 0u);
+      const R dh0 = (ej - ei) - td;
+      const R dH = dh0 - Ef * (R)cdx[k];
+      const bool acc = th & metropolis_nb(dH, cu[k], th, S);
+      theta_cnt += th ? 1u : 0u;
+      if (acc) {
+        first = k;
+        fi = i;
+        fj = j;
+        fdx = cdx[k];
+        fdh0 = (double)dh0;
       }
     }
+    // the wave's lowest accepting lane publishes (key, i, j) with one 64-bit LDS min; the
+    // round's minimum is the workgroup's lowest accepted label (i, j < 2^16 since N <= 36864)
     const unsigned long long bal = __ballot(first < U);
     if (bal != 0ull) {
       const int wl = __ffsll(bal) - 1;
@@ -269,27 +377,27 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         h.key = (uint32_t)(tid * U + first);
         h.i = fi;
         h.j = fj;
-        h.v = fv;
+        h.v = 0;
         h.dH0 = fdh0;
+        h.pad[0] = fdx;
         info[wid] = h;
-        atomicOr(&sh->wmask[it % 3], 1u << wid);
+        atomicMin(&sh->best[it % 3], ((uint64_t)h.key << 32) | ((uint64_t)fi << 16) | (uint64_t)fj);
       }
     }
-    if (tid == 0) {
-      sh->wmask[(it + 1) % 3] = 0u;
-      sh->rounds += 1;
-      sh->evaluated += active;
-    }
+    if (tid == 0) sh->best[(it + 1) % 3] = ~0ull;
     __syncthreads();
-    const uint32_t wmask = __builtin_amdgcn_readfirstlane(sh->wmask[it % 3]);
+    const uint64_t best = uni(sh->best[it % 3]);
     ++it;
+    ++rounds;
+    evaluated += active;
+    CG_MARK(tc1)
 
-    if (wmask == 0u) {
+    if (best == ~0ull) {
       // no accepted label in this chunk: every label in it is decided (rejected)
       done = base + M;
       base = done;
       cached = false;
-      if (done - gs->call_scan0 >= ra.max_labels) {
+      if (done - scan0 >= ra.max_labels) {
         status = -4;  // CG_ESTALL
         break;
       }
@@ -297,74 +405,153 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
     }
 
     // X: execute the lowest accepted label of the chunk
-    const HopInfo h = info[__ffs(wmask) - 1];
+    HopInfo h;
+    h.key = (uint32_t)(best >> 32);
+    h.i = (int)((best >> 16) & 0xffffu);
+    h.j = (int)(best & 0xffffu);
+    {
+      const HopInfo& w = info[(h.key / U) >> 6];  // written by the winning wave
+      h.dH0 = uni(w.dH0);
+      h.pad[0] = uni(w.pad[0]);
+    }
+    const int hdx = h.pad[0];
     const uint64_t q = base + 1 + (uint64_t)h.key;
     const uint64_t m = q - s_last;
     s_last = q;
     done = q;
     ++hops;
     ++since;
+    P += hdx;
+    H0 = H0 + h.dH0;
+    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
     if (tid == 0) {
-      occ[h.i >> 5] &= ~(1u << (h.i & 31));
-      occ[h.j >> 5] |= 1u << (h.j & 31);
-      const int hv = vec[h.v];
-      sh->P += (int64_t)(int16_t)(hv & 0xffff);
-      sh->H0 = sh->H0 + h.dH0;
-      sh->sum_p += (m + M - 1) / M;
-      const int64_t lg = sh->logged;
-      if (lg < S.log_cap) {
-        S.log_label[lg] = q;
-        S.log_from[lg] = h.i;
-        S.log_to[lg] = h.j;
-        sh->logged = lg + 1;
+      atomicAnd(&occ[h.i >> 5], ~(1u << (h.i & 31)));
+      atomicOr(&occ[h.j >> 5], 1u << (h.j & 31));
+      if (logged < S.log_cap) {
+        S.log_label[logged] = q;
+        S.log_from[logged] = h.i;
+        S.log_to[logged] = h.j;
       }
-      if (ra.clock_mode == 0) {
-        sh->t = (double)s_last / S.Gamma;
-      } else {
-        uint32_t c0 = (uint32_t)hops, c1 = (uint32_t)(hops >> 32), c2 = sid, c3 = kTagClock;
-        philox10(c0, c1, c2, c3, k0, k1);
-        const double u1 = unit52(c0, c1), u2 = unit52(c2, c3);
-        const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-        const double mean = (double)m / S.Gamma;
-        const double sd = sqrt((double)m) / S.Gamma;
-        double dt = mean + sd * z;
-        if (dt < 0.0) dt = 0.0;
-        sh->t = sh->t + dt;
+      if (ra.clock_mode != 0) sh->t = sh->t + gauss_dt(hops, m, sid, k0, k1, S.Gamma);
+    }
+    if (logged < S.log_cap) ++logged;
+    CG_MARK(tc2)
+
+    // U: step 3b on the owned sites.  All table loads are issued before the first use;
+    // in an inexact geometry, rows/columns beyond L read a valid table entry and store to a
+    // dummy LDS word, so no lane branches.
+    {
+      const int yi = row_of(h.i, magic), xi = h.i - yi * L;
+      const int yj = row_of(h.j, magic), xj = h.j - yj * L;
+      int cjx[NC], cix[NC], tjx[NC], tix[NC], sto[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = lane + 64 * c;
+        const bool xv = EXACT || x < L;
+        cjx[c] = xv ? fold(x - xj, L) : 0;
+        cix[c] = xv ? fold(x - xi, L) : 0;
+        tjx[c] = TRI ? tri_of<TRI>(cjx[c]) : 0;
+        tix[c] = TRI ? tri_of<TRI>(cix[c]) : 0;
+        sto[c] = xv ? x : -1;
+      }
+      // rows in groups of RG: every load of a group is issued before its first use
+      constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : 4;
+#pragma unroll
+      for (int r0 = 0; r0 < RPW; r0 += RG) {
+        R d[RG][NC];
+        ET e[MODE == kModeReg ? 1 : RG][NC];
+#pragma unroll
+        for (int rr = 0; rr < RG; ++rr) {
+          const int y = wid + NW * (r0 + rr);
+          const bool yv = EXACT || y < L;
+          const int ayj = yv ? fold(y - yj, L) : 0, ayi = yv ? fold(y - yi, L) : 0;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            int kj, ki;
+            if (TRI) {
+              kj = cjx[c] >= ayj ? tjx[c] + ayj : tri_of<TRI>(ayj) + cjx[c];
+              ki = cix[c] >= ayi ? tix[c] + ayi : tri_of<TRI>(ayi) + cix[c];
+            } else {
+              kj = ayj * H1 + cjx[c];
+              ki = ayi * H1 + cix[c];
+            }
+            d[rr][c] = tab[kj] - tab[ki];
+            if constexpr (MODE != kModeReg)
+              if (EXACT || (yv && sto[c] >= 0)) e[rr][c] = es[y * L + lane + 64 * c];
+          }
+        }
+#pragma unroll
+        for (int rr = 0; rr < RG; ++rr) {
+          const int r = r0 + rr;
+          const int y = wid + NW * r;
+          const bool yv = EXACT || y < L;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            if constexpr (MODE == kModeReg) {
+              E[r][c] = Energy<R>::add(E[r][c], d[rr][c]);
+              R* dst = (EXACT || (yv && sto[c] >= 0)) ? ev + (y * L + lane + 64 * c) : (R*)&sh->dummy;
+              *dst = Energy<R>::value(E[r][c]);
+            } else {
+              if (EXACT || (yv && sto[c] >= 0)) es[y * L + lane + 64 * c] = Energy<R>::add(e[rr][c], d[rr][c]);
+            }
+          }
+        }
       }
     }
-    update_energies<R, TRI>(eps, tab, h.i, h.j, L, H1, magic, lane, wid, nw);
     __syncthreads();
+    CG_MARK(tc3)
     if (done == base + M) {
       base = done;
       cached = false;
     }
-    if (hops >= gs->hop_target) break;
-    if (ra.time_mode && sh->t >= gs->t_end) break;
+    if (hops >= target) break;
+    if (ra.time_mode) {
+      if (ra.clock_mode == 0 ? s_last >= s_end : uni(sh->t) >= t_end) break;
+    }
     if (ra.K > 0 && since >= ra.K) break;
   }
 
   atomicAdd(&sh->theta, theta_cnt);
-  __syncthreads();
   {
-    R* g = (R*)S.eps;
-    for (int k = tid; k < N; k += nthr) g[k] = eps[k];
+    ET* __restrict__ g = (ET*)S.eps;
+    if constexpr (MODE == kModeReg) {
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int y = wid + NW * r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int x = lane + 64 * c;
+          if (y < L && x < L) g[y * L + x] = E[r][c];
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (MODE == kModeLds)
+      for (int k = tid; k < N; k += 1024) g[k] = es[k];
   }
-  for (int k = tid; k < S.NW; k += nthr) S.occ[k] = occ[k];
+  for (int k = tid; k < S.NW; k += 1024) S.occ[k] = occ[k];
   if (tid == 0) {
     gs->hops = hops;
     gs->s_last = s_last;
     gs->s_scan = done;
-    gs->P = sh->P;
-    gs->t = sh->t;
-    gs->H0 = sh->H0;
+    gs->P = P;
+    gs->t = ra.clock_mode == 0 ? (double)s_last / S.Gamma : sh->t;
+    gs->H0 = H0;
     gs->since_refresh = since;
     gs->status = status;
-    gs->sum_p = sh->sum_p;
-    gs->rounds = sh->rounds;
-    gs->evaluated = sh->evaluated;
+    gs->sum_p = sum_p;
+    gs->rounds = rounds;
+    gs->evaluated = evaluated;
     gs->theta_pass += sh->theta;
-    gs->logged = sh->logged;
+    gs->logged = logged;
+    if (timers) {
+      gs->phase_cycles[0] += tc0;
+      gs->phase_cycles[1] += tc1;
+      gs->phase_cycles[2] += tc2;
+      gs->phase_cycles[3] += tc3;
+    }
   }
+#undef CG_MARK
 }
 
 // ---------------------------------------------------------------------------------
@@ -432,7 +619,7 @@ __global__ void __launch_bounds__(kInitBlock) k_eps_exact(const DevSample* __res
   if ((int)(blockIdx.x * kInitBlock) >= N) return;
   if (refresh) {
     const SampleState* st = S.st;
-    if (!(st->force_refresh || (K > 0 && st->since_refresh >= K))) return;
+    if (S.dft || !(st->force_refresh || (K > 0 && st->since_refresh >= K))) return;
   }
   extern __shared__ __align__(16) uint8_t smem[];
   uint32_t* occ = (uint32_t*)smem;
@@ -459,9 +646,9 @@ __global__ void __launch_bounds__(kInitBlock) k_eps_exact(const DevSample* __res
         acc = acc + q * row[fold(xl - xm, L)];
       }
     }
-    R* e = (R*)S.eps;
-    if (refresh) drift = fabs((double)e[l] - acc);
-    e[l] = (R)acc;
+    typename Energy<R>::T* e = (typename Energy<R>::T*)S.eps;
+    if (refresh) drift = fabs((double)Energy<R>::value(e[l]) - acc);
+    e[l] = Energy<R>::from64(acc);
     const bool nl = (occ[l >> 5] >> (l & 31)) & 1u;
     const double ph = S.phi[l];
     contrib = (nl ? ph : 0.0) + 0.5 * ((nl ? q1 : q0) * (acc - ph));
@@ -482,12 +669,170 @@ __global__ void __launch_bounds__(kInitBlock) k_eps_exact(const DevSample* __res
   }
 }
 
+// ---------------------------------------------------------------------------------
+// FP64 refresh by Fourier transform along x.  The energies of step 3b's definition are
+// a circular convolution on the torus, eps = phi + (n - nu) (*) T with T(0) = 0, so with
+// Q(k, y) = sum_x (n - nu)(x, y) e^{-2 pi i k x / L} and That(k, dy) = sum_dx T(dx, dy)
+// cos(2 pi k dx / L) (real: T is even in dx):
+//   C(k, y)   = sum_y' That(k, y - y') Q(k, y')                   (per-frequency convolution)
+//   eps(x, y) = phi(x, y) + (1/L) sum_k w_k Re[C(k, y) e^{2 pi i k x / L}],
+// k = 0..L/2 with w_k = 2 except w_0 = 1 and, for even L, w_{L/2} = 1.  Frequencies are
+// processed in chunks of KC that fit LDS; every thread owns the outputs (x, g + G r) and
+// accumulates them in registers over the chunks.  One workgroup per sample; samples not
+// due a refresh return at once.  Records max |eps32 - eps64|, writes fl(eps64), recomputes
+// the energy total in FP64.
+constexpr int kDftRowsMax = 32;  // outputs per thread: ceil(L / floor(1024 / L)) <= 32
+constexpr int kDftItems = 4;     // convolution items per thread: KC * L <= 4 * 1024
+
+template <typename R, int kDftRows>
+__global__ void __launch_bounds__(1024) k_refresh_dft(const DevSample* __restrict__ samples, int K) {
+  const DevSample& S = samples[blockIdx.x];
+  SampleState* __restrict__ st = S.st;
+  if (!S.dft || ((S.dft_rows > 16) != (kDftRows > 16))) return;
+  if (!(st->force_refresh || (K > 0 && st->since_refresh >= K))) return;
+  const int L = S.L, NK = S.H + 1, KC = S.dft_kc;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  extern __shared__ __align__(16) uint8_t smem[];
+  uint32_t* __restrict__ occ = (uint32_t*)smem;
+  double2* __restrict__ tw = (double2*)(smem + align16(S.NW * 4));
+  double2* __restrict__ Q = tw + L;
+  double* __restrict__ Th = (double*)(Q + KC * L);
+  __shared__ double red_h[kMaxWaves], red_d[kMaxWaves];
+  for (int k = tid; k < S.NW; k += nthr) occ[k] = S.occ[k];
+  for (int k = tid; k < L; k += nthr) tw[k] = ((const double2*)S.dft_tw)[k];
+
+  const double q1 = 1.0 - S.nu, q0 = 0.0 - S.nu;
+  const int G = nthr / L;
+  const int x = tid % L, g = tid / L;
+  const bool owner = g < G;
+  double acc[kDftRows];
+#pragma unroll
+  for (int r = 0; r < kDftRows; ++r) acc[r] = 0.0;
+
+  for (int k0 = 0; k0 < NK; k0 += KC) {
+    const int kc = NK - k0 < KC ? NK - k0 : KC;
+    const int items = kc * L;
+    __syncthreads();
+    for (int w = tid; w < items; w += nthr) Th[w] = S.dft_T[(size_t)k0 * L + w];
+    // forward transform along x: item w = (frequency k0 + w / L, row w % L)
+    for (int w = tid; w < items; w += nthr) {
+      const int kk = w / L, y = w - kk * L, k = k0 + kk;
+      double re = 0.0, im = 0.0;
+      int idx = 0;
+      const uint32_t* orow = occ;
+      for (int xx = 0; xx < L; ++xx) {
+        const int m = y * L + xx;
+        const double qv = ((orow[m >> 5] >> (m & 31)) & 1u) ? q1 : q0;
+        const double2 t = tw[idx];
+        re = re + qv * t.x;
+        im = im - qv * t.y;
+        idx += k;
+        idx -= idx >= L ? L : 0;
+      }
+      Q[w] = make_double2(re, im);
+    }
+    __syncthreads();
+    // convolution along y, into registers, then back into Q
+    double2 res[kDftItems];
+#pragma unroll
+    for (int r = 0; r < kDftItems; ++r) {
+      const int w = tid + r * nthr;
+      res[r] = make_double2(0.0, 0.0);
+      if (w < items) {
+        const int kk = w / L, y = w - kk * L;
+        const double* th = Th + kk * L;
+        const double2* qk = Q + kk * L;
+        double re = 0.0, im = 0.0;
+        int d = y;
+        for (int yp = 0; yp < L; ++yp) {
+          const double t = th[d];
+          const double2 qv = qk[yp];
+          re = re + t * qv.x;
+          im = im + t * qv.y;
+          d = d == 0 ? L - 1 : d - 1;
+        }
+        res[r] = make_double2(re, im);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kDftItems; ++r) {
+      const int w = tid + r * nthr;
+      if (w < items) Q[w] = res[r];
+    }
+    __syncthreads();
+    // inverse transform along x, accumulated per owned output
+    if (owner) {
+      int idx = (int)(((int64_t)k0 * x) % L);
+      for (int kk = 0; kk < kc; ++kk) {
+        const int k = k0 + kk;
+        const double wk = (k == 0 || 2 * k == L) ? 1.0 : 2.0;
+        const double2 t = tw[idx];
+        const double c = wk * t.x, sn = wk * t.y;
+        const double2* ck = Q + kk * L;
+#pragma unroll
+        for (int r = 0; r < kDftRows; ++r) {
+          const int y = g + G * r;
+          if (y < L) {
+            const double2 cv = ck[y];
+            acc[r] = acc[r] + (cv.x * c - cv.y * sn);
+          }
+        }
+        idx += x;
+        idx -= idx >= L ? L : 0;
+      }
+    }
+  }
+
+  double hsum = 0.0, dmax = 0.0;
+  if (owner) {
+    const double invL = 1.0 / (double)L;
+    typename Energy<R>::T* e = (typename Energy<R>::T*)S.eps;
+#pragma unroll
+    for (int r = 0; r < kDftRows; ++r) {
+      const int y = g + G * r;
+      if (y < L) {
+        const int l = y * L + x;
+        const double ph = S.phi[l];
+        const double e64 = ph + acc[r] * invL;
+        dmax = fmax(dmax, fabs((double)Energy<R>::value(e[l]) - e64));
+        e[l] = Energy<R>::from64(e64);
+        const bool nl = (occ[l >> 5] >> (l & 31)) & 1u;
+        hsum = hsum + ((nl ? ph : 0.0) + 0.5 * ((nl ? q1 : q0) * (e64 - ph)));
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    hsum += __shfl_xor(hsum, off);
+    dmax = fmax(dmax, __shfl_xor(dmax, off));
+  }
+  const int lane = tid & 63, wv = tid >> 6;
+  if (lane == 0) {
+    red_h[wv] = hsum;
+    red_d[wv] = dmax;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double h = 0.0, d = 0.0;
+    for (int k = 0; k < (nthr >> 6); ++k) {
+      h = h + red_h[k];
+      d = fmax(d, red_d[k]);
+    }
+    st->H0 = h;
+    st->refreshes += 1;
+    st->last_drift = d;
+    st->max_drift = fmax(st->max_drift, d);
+    st->since_refresh = 0;
+    st->force_refresh = 0;
+  }
+}
+
 // Folds the per-block partials of k_eps_exact into the sample state (one block per sample).
 __global__ void __launch_bounds__(64) k_finalize(const DevSample* __restrict__ samples, int refresh, int K) {
   const DevSample& S = samples[blockIdx.x];
   SampleState* st = S.st;
   if (threadIdx.x != 0) return;
-  if (refresh && !(st->force_refresh || (K > 0 && st->since_refresh >= K))) return;
+  if (refresh && (S.dft || !(st->force_refresh || (K > 0 && st->since_refresh >= K)))) return;
   double h = 0.0, d = 0.0;
   for (int b = 0; b < S.nblk; ++b) {
     h = h + S.part[b];

@@ -1,8 +1,8 @@
 // layout.hpp -- data structures shared by the host side and the kernels of libcgkmc.
 //
-// Per sample, the arena holds (each block 256-byte aligned):
-//   SampleState                          counters, clock, energy totals, run targets
-//   eps   [N]    float | double          local energies (the form's precision)
+// The arena holds one SampleState per sample (counters, clock, energy totals, run targets)
+// in a contiguous array, and per sample (each block 256-byte aligned):
+//   eps   [N]    double | float2         local energies (FP64, or FP32 value + Kahan low part)
 //   phi   [N]    double                  disorder (scratch for init keys before that)
 //   occ   [NW]   u32                     occupation bits, site l -> word l>>5, bit l&31
 //   tab64 [(H+1)^2] double               1/r by folded separation (|dy|, |dx|), H = L/2
@@ -11,6 +11,7 @@
 //   orb   [n_orb] u32                    first member | (orbit size - 1) << 16
 //   vec   [n_vec] i32                    member displacement (dx & 0xffff) | dy << 16
 //   guide [1024] u8                      orbit at the start of each 2^22-wide bucket of w1
+//   dft_tw [L] double2, dft_T [(H+1) L] double   twiddles and transformed 1/r for the refresh
 //   part  [2 * nblk] double              per-block partial sums (energy, drift)
 //   log   [cap] u64 + 2 x [cap] i32      executed-hop log (label, from, to)
 #pragma once
@@ -49,12 +50,14 @@ struct SampleState {
   int32_t since_refresh;  // hops since last refresh
   int32_t force_refresh;  // refresh kernel: refresh regardless of since_refresh
   int32_t pad_;
+  uint64_t phase_cycles[4];  // shader cycles: refill, evaluate, execute, update (if timed)
 };
 
 struct DevSample {
   int32_t L, N, H, n_e;
   int32_t NW, n_orb, n_vec, ntab;   // ntab: entries of the hop kernel's table
-  int32_t nblk, log_cap, layout, pad_;
+  int32_t nblk, log_cap, layout, dft;  // dft: refresh by Fourier transform along x
+  int32_t dft_kc, dft_rows, pad2_[2];   // frequencies per LDS chunk, outputs per thread
   uint32_t seed_lo, seed_hi, sample_id, magic_L;  // magic_L = ceil(2^32 / L)
   double nu, W, T, E, Gamma;
   float T32, E32, invT32, pad32_;
@@ -69,6 +72,8 @@ struct DevSample {
   const int32_t* vec;
   const uint8_t* guide;
   double* part;
+  const double* dft_tw;   // [L] (cos, sin)(2 pi j / L)
+  const double* dft_T;    // [(H+1) x L] sum_dx T(dx, dy) cos(2 pi k dx / L), row k
   uint64_t* log_label;
   int32_t* log_from;
   int32_t* log_to;
@@ -76,10 +81,12 @@ struct DevSample {
 
 // Knobs of one hop-kernel launch (uniform over the batch).
 struct RunArgs {
-  int32_t M;            // labels per parallel iteration = block * labels_per_lane
+  int32_t M;            // labels per parallel iteration = block * labels_per_lane (power of 2)
+  int32_t log2M;
   int32_t K;            // FP32 form: stop a sample when since_refresh reaches K (0: never)
   int32_t time_mode;    // 1: stop after the hop that brings t >= t_end
   int32_t clock_mode;   // 0: t = s_last / Gamma ; 1: Gaussian increments
+  int32_t timers;       // 1: accumulate per-phase shader cycles
   uint64_t max_labels;  // per-call label cap (stall guard)
 };
 
@@ -93,10 +100,10 @@ struct HopLds {
 constexpr int32_t kInfoBytes = 32;
 
 __host__ __device__ inline HopLds hop_lds(int32_t N, int32_t NW, int32_t ntab, int32_t n_vec,
-                                          int32_t n_orb, int32_t real_bytes) {
+                                          int32_t n_orb, int32_t energy_bytes, int32_t real_bytes) {
   HopLds o;
   int32_t b = 0;
-  o.eps = b;   b = align16(b + N * real_bytes);
+  o.eps = b;   b = align16(b + N * energy_bytes);
   o.occ = b;   b = align16(b + NW * 4);
   o.tab = b;   b = align16(b + ntab * real_bytes);
   o.vec = b;   b = align16(b + n_vec * 4);

@@ -68,7 +68,7 @@ def test_arena_bytes_and_validation():
             cg.arena_bytes([d], cg.make_opts())
         assert e.value.code == cg.CG_EINVAL
         assert cg.load().cg_last_error()
-    for o in (cg.make_opts(block=300), cg.make_opts(M=1000), cg.make_opts(block=256, M=256 * 16),
-              cg.make_opts(precision=7), cg.make_opts(clock_mode=5)):
+    for o in (cg.make_opts(block=300), cg.make_opts(M=1000), cg.make_opts(block=256),
+              cg.make_opts(precision=7), cg.make_opts(clock_mode=5), cg.make_opts(phase_timers=3)):
         with pytest.raises(cg.CgError):
             cg.arena_bytes(serial_small(), o)
