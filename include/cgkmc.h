@@ -82,6 +82,10 @@ typedef struct cg_run_opts {
   int32_t use_graph;   /* 1: cg_run_hops captures its launch sequence once per (n_hops,
                           refresh phase) as a hipGraph and replays it; needs a stream
                           other than the legacy default stream                          */
+  int32_t variant;     /* hop kernel: 0 = automatic; 1 = two workgroup barriers per hop;
+                          2 = one barrier per hop (FP32 form, L <= 128: double-buffered
+                          energies, the next round corrects for the hop in flight)      */
+  int32_t reserved;    /* set to 0                                                       */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;
 

@@ -200,7 +200,8 @@ struct SampleLayout {
 
 struct Plan {
   int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0, timers = 0;
-  int32_t use_graph = 0;
+  int32_t use_graph = 0, variant = 0;
+  bool use_db = false;
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
   uint64_t max_labels = 1ull << 32;
@@ -253,6 +254,8 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.timers = o->phase_timers;
   if (o->use_graph != 0 && o->use_graph != 1) return set_err(CG_EINVAL, "use_graph=%d", o->use_graph);
   p.use_graph = o->use_graph;
+  if (o->variant < 0 || o->variant > 2) return set_err(CG_EINVAL, "variant=%d", o->variant);
+  p.variant = o->variant;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
   if (p.precision == CG_FP64) p.K = 0;
@@ -269,7 +272,8 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     if (rc != CG_OK) return rc;
   }
   // table layout: full (|dy|,|dx|) table if every sample fits, else the triangle
-  bool full_fits = true, tri_fits = true;
+  bool full_fits = true, tri_fits = true, db_fits = true;
+  int32_t need_db = 0;
   int32_t max_L_all = 0;
   for (int32_t b = 0; b < n; ++b) max_L_all = std::max(max_L_all, s[b].L);
   int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
@@ -287,10 +291,22 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     need_tri = std::max(need_tri, t);
     full_fits = full_fits && f <= lds_cap;
     tri_fits = tri_fits && t <= lds_cap;
+    // one-barrier FP32 kernel: two buffers of FP32 value words
+    const int32_t dbb = hop_lds(N, NW, full_entries(H), n_vec, n_orb, 8, 4).total;
+    need_db = std::max(need_db, dbb);
+    db_fits = db_fits && dbb <= lds_cap;
     need_exact = std::max(need_exact, align16(NW * 4) + full_entries(H) * 8);
     max_N = std::max(max_N, N);
   }
-  if (full_fits) {
+  // automatic choice: two barriers (measured faster at L = 128: 81e6 vs 75e6 hops/s)
+  p.use_db = p.precision == CG_FP32_REFRESH && max_L_all <= 128 && db_fits && p.variant == 2;
+  if (p.variant == 2 && !p.use_db)
+    return set_err(CG_EINVAL, "variant 2 (one barrier per hop) needs the FP32 form, L <= 128 and %d bytes of LDS",
+                   need_db);
+  if (p.use_db) {
+    p.layout = kFull;
+    p.lds_hop = need_db;
+  } else if (full_fits) {
     p.layout = kFull;
     p.lds_hop = need_full;
   } else if (tri_fits && p.precision == CG_FP64) {
@@ -375,7 +391,17 @@ HopFn pick_geo(int32_t NC, bool exact) {
   return exact ? k_hops<R, U, TRI, 2, 8, true, MODE> : k_hops<R, U, TRI, 2, 8, false, MODE>;
 }
 
-HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact) {
+HopFn pick_db(int32_t U, int32_t NC, bool exact) {
+  if (NC == 1) {
+    if (U == 1) return exact ? k_hops_db<1, 1, 4, true> : k_hops_db<1, 1, 4, false>;
+    return exact ? k_hops_db<2, 1, 4, true> : k_hops_db<2, 1, 4, false>;
+  }
+  if (U == 1) return exact ? k_hops_db<1, 2, 8, true> : k_hops_db<1, 2, 8, false>;
+  return exact ? k_hops_db<2, 2, 8, true> : k_hops_db<2, 2, 8, false>;
+}
+
+HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db) {
+  if (db) return pick_db(U, NC, exact);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
     return k_hops<float, 1, false, 3, 12, false, kModeGlobal>;
@@ -591,7 +617,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   c->d_samples = (DevSample*)(c->arena + p.samples_off);
   c->d_order = (int32_t*)(c->arena + p.order_off);
   c->d_pending = (int32_t*)(c->arena + p.scratch_off);
-  c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact);
+  c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db);
 
   auto fail = [&](int code) {
     delete c;

@@ -173,6 +173,43 @@ __device__ __noinline__ uint64_t label_at_time(double t_end, double Gamma) {
   return s;
 }
 
+// Step 1 for this lane's labels base + 1 + tid U + k, k < U: Philox4x32-10 of (label,
+// sample, PROPOSE) gives the site i = mulhi(w0, N), the displacement orbit (first o with
+// w1 < thr[o], started from the guide bucket of w1) and member (w3 & (size - 1)), and the
+// acceptance uniform; cached as (i, j, 1/r table index, dx, u).
+template <typename R, int U, bool TRI>
+__device__ __forceinline__ void draw_labels(uint64_t base, int tid, const DevSample& S, const uint8_t* guide,
+                                            const uint32_t* thr, const uint32_t* orb, const int32_t* vec,
+                                            int (&ci)[U], int (&cj)[U], int (&ct)[U], int (&cdx)[U],
+                                            R (&cu)[U]) {
+  const int L = S.L, N = S.N, H1 = S.H + 1, n_orb = S.n_orb;
+  const uint32_t magic = S.magic_L;
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
+    uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = S.sample_id, c3 = kTagPropose;
+    philox10(c0, c1, c2, c3, S.seed_lo, S.seed_hi);
+    const int i = (int)__umulhi(c0, (uint32_t)N);
+    int o = guide[c1 >> (32 - kGuideBits)];
+    while (o < n_orb - 1 && c1 >= thr[o]) ++o;
+    const uint32_t ob = orb[o];
+    const int v = (int)(ob & 0xffffu) + (int)(c3 & (ob >> 16));
+    const int pv = vec[v];
+    const int dx = (int)(int16_t)(pv & 0xffff), dy = pv >> 16;
+    const int yi = row_of(i, magic), xi = i - yi * L;
+    int xj = xi + dx, yj = yi + dy;
+    xj += xj < 0 ? L : 0;
+    xj -= xj >= L ? L : 0;
+    yj += yj < 0 ? L : 0;
+    yj -= yj >= L ? L : 0;
+    ci[k] = i;
+    cj[k] = yj * L + xj;
+    ct[k] = tidx<TRI>(dy < 0 ? -dy : dy, dx < 0 ? -dx : dx, H1);
+    cdx[k] = dx;
+    cu[k] = accept_uniform<R>(c2, c3);
+  }
+}
+
 // Workgroup-shared control words: per-round bitmask of waves holding an accepted label
 // (triple-buffered, see the round loop), the clock of the Gaussian mode, theta count.
 struct HopShared {
@@ -306,30 +343,7 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
   for (;;) {
     // P: draw this lane's labels of the chunk once; they are re-used after a hop
     if (!cached) {
-#pragma unroll
-      for (int k = 0; k < U; ++k) {
-        const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
-        uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = sid, c3 = kTagPropose;
-        philox10(c0, c1, c2, c3, k0, k1);
-        const int i = (int)__umulhi(c0, (uint32_t)N);
-        int o = guide[c1 >> (32 - kGuideBits)];
-        while (o < n_orb - 1 && c1 >= thr[o]) ++o;
-        const uint32_t ob = orb[o];
-        const int v = (int)(ob & 0xffffu) + (int)(c3 & (ob >> 16));
-        const int pv = vec[v];
-        const int dx = (int)(int16_t)(pv & 0xffff), dy = pv >> 16;
-        const int yi = row_of(i, magic), xi = i - yi * L;
-        int xj = xi + dx, yj = yi + dy;
-        xj += xj < 0 ? L : 0;
-        xj -= xj >= L ? L : 0;
-        yj += yj < 0 ? L : 0;
-        yj -= yj >= L ? L : 0;
-        ci[k] = i;
-        cj[k] = yj * L + xj;
-        ct[k] = tidx<TRI>(dy < 0 ? -dy : dy, dx < 0 ? -dx : dx, H1);
-        cdx[k] = dx;
-        cu[k] = accept_uniform<R>(c2, c3);
-      }
+      draw_labels<R, U, TRI>(base, tid, S, guide, thr, orb, vec, ci, cj, ct, cdx, cu);
       cached = true;
       CG_MARK(tc0)
     }
@@ -529,6 +543,338 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
     if constexpr (MODE == kModeLds)
       for (int k = tid; k < N; k += 1024) g[k] = es[k];
   }
+  for (int k = tid; k < S.NW; k += 1024) S.occ[k] = occ[k];
+  if (tid == 0) {
+    gs->hops = hops;
+    gs->s_last = s_last;
+    gs->s_scan = done;
+    gs->P = P;
+    gs->t = ra.clock_mode == 0 ? (double)s_last / S.Gamma : sh->t;
+    gs->H0 = H0;
+    gs->since_refresh = since;
+    gs->status = status;
+    gs->sum_p = sum_p;
+    gs->rounds = rounds;
+    gs->evaluated = evaluated;
+    gs->theta_pass += sh->theta;
+    gs->logged = logged;
+    if (timers) {
+      gs->phase_cycles[0] += tc0;
+      gs->phase_cycles[1] += tc1;
+      gs->phase_cycles[2] += tc2;
+      gs->phase_cycles[3] += tc3;
+    }
+  }
+#undef CG_MARK
+}
+
+// ---------------------------------------------------------------------------------
+// FP32 hop kernel with one workgroup barrier per hop.  The value words of the energies are
+// double-buffered in LDS.  When the round ending at barrier B_r selects hop h, each wave
+// runs step 3b for h on its owned sites (registers, Kahan) and writes the new values into
+// the buffer not being read, while the next round evaluates its labels against the other
+// buffer (energies before h) plus hop h's own contribution, 1/r_xj - 1/r_xi, computed by
+// each lane for its two sites, and with the occupation of h's two sites overridden.  The
+// update is complete at the next barrier, where the buffers swap.  The executed hops are
+// those of the two-barrier kernel (same labels, same decisions up to FP32 rounding).
+template <int U, int NC, int RPW, bool EXACT>
+__global__ void __launch_bounds__(1024) k_hops_db(const DevSample* __restrict__ samples,
+                                                  const int32_t* __restrict__ order, RunArgs ra) {
+  using R = float;
+  using ET = float2;
+  constexpr int NW = 16;
+  const DevSample& S = samples[order[blockIdx.x]];
+  SampleState* __restrict__ gs = S.st;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  uint64_t hops = uni(gs->hops);
+  uint64_t s_last = uni(gs->s_last);
+  uint64_t done = uni(gs->s_scan);
+  int32_t since = uni(gs->since_refresh);
+  const uint64_t target = uni(gs->hop_target);
+  const uint64_t scan0 = uni(gs->call_scan0);
+  const double t_end = uni(gs->t_end);
+  const double t_start = uni(gs->t);
+  {
+    const bool idle = uni(gs->status) != 0 || hops >= target || (ra.time_mode && t_start >= t_end) ||
+                      (ra.K > 0 && since >= ra.K);
+    if (idle) return;
+  }
+  int64_t P = uni(gs->P);
+  double H0 = uni(gs->H0);
+  uint64_t sum_p = uni(gs->sum_p), rounds = uni(gs->rounds), evaluated = uni(gs->evaluated);
+  int64_t logged = uni(gs->logged);
+  int32_t status = 0;
+
+  const int L = S.L, N = S.N, H1 = S.H + 1, n_orb = S.n_orb;
+  const uint32_t magic = S.magic_L;
+  extern __shared__ __align__(16) uint8_t smem[];
+  const HopLds lo = hop_lds(N, S.NW, S.ntab, S.n_vec, n_orb, 2 * (int32_t)sizeof(R), (int32_t)sizeof(R));
+  R* __restrict__ buf = (R*)(smem + lo.eps);  // two value buffers of N words
+  uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
+  R* __restrict__ tab = (R*)(smem + lo.tab);
+  int32_t* __restrict__ vec = (int32_t*)(smem + lo.vec);
+  uint32_t* __restrict__ thr = (uint32_t*)(smem + lo.thr);
+  uint32_t* __restrict__ orb = (uint32_t*)(smem + lo.orb);
+  uint8_t* __restrict__ guide = smem + lo.guide;
+  HopShared* __restrict__ sh = (HopShared*)(smem + lo.ctrl);
+  HopInfo* __restrict__ info = (HopInfo*)(smem + lo.info);  // [2][16], by round parity
+
+  ET E[RPW][NC];
+  {
+    const ET* __restrict__ g = (const ET*)S.eps;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int y = wid + NW * r;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = lane + 64 * c;
+        if (y < L && x < L) {
+          E[r][c] = g[y * L + x];
+          buf[y * L + x] = E[r][c].x;
+        } else {
+          E[r][c] = ET();
+        }
+      }
+    }
+    const R* gt = (const R*)S.tabk;
+    for (int k = tid; k < S.ntab; k += 1024) tab[k] = gt[k];
+  }
+  for (int k = tid; k < S.NW; k += 1024) occ[k] = S.occ[k];
+  for (int k = tid; k < S.n_vec; k += 1024) vec[k] = S.vec[k];
+  for (int k = tid; k < n_orb; k += 1024) {
+    thr[k] = S.thr[k];
+    orb[k] = S.orb[k];
+  }
+  for (int k = tid; k < kGuideSize; k += 1024) guide[k] = S.guide[k];
+  if (tid == 0) {
+    sh->best[0] = sh->best[1] = sh->best[2] = ~0ull;
+    sh->theta = 0u;
+    sh->t = t_start;
+  }
+  __syncthreads();
+
+  const uint32_t sid = S.sample_id, k0 = S.seed_lo, k1 = S.seed_hi;
+  const uint64_t M = (uint64_t)(1024 * U);
+  const uint64_t s_end = uni((ra.time_mode && ra.clock_mode == 0) ? label_at_time(t_end, S.Gamma) : (uint64_t)0);
+  const R Ef = S.E32;
+  uint64_t base = done;
+  bool cached = false;
+  int ci[U], cj[U], ct[U], cdx[U];
+  R cu[U];
+  uint32_t theta_cnt = 0;
+  uint32_t it = 0;
+  int cur = 0;          // buffer holding the energies after every completed update
+  bool pend = false;    // a hop's update runs in this round (writes buffer cur ^ 1)
+  int pi = 0, pj = 0;   // the pending hop
+  uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
+  const bool timers = ra.timers != 0;
+#define CG_MARK(acc)                                          \
+  if (timers) {                                               \
+    const uint64_t now_ = __builtin_amdgcn_s_memtime();       \
+    acc += now_ - tmark;                                      \
+    tmark = now_;                                             \
+  }
+  if (timers) tmark = __builtin_amdgcn_s_memtime();
+
+  // per-hop constants of the pending hop for the lanes' own-site corrections
+  int pxi = 0, pyi = 0, pxj = 0, pyj = 0;
+
+  for (;;) {
+    if (!cached) {
+      draw_labels<R, U, false>(base, tid, S, guide, thr, orb, vec, ci, cj, ct, cdx, cu);
+      cached = true;
+      CG_MARK(tc0)
+    }
+    R* __restrict__ rd = buf + (cur ? N : 0);
+    // U: step 3b of the pending hop on the owned sites, into the other buffer
+    if (pend) {
+      R* __restrict__ wr = buf + (cur ? 0 : N);
+      int cjx[NC], cix[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = lane + 64 * c;
+        const bool xv = EXACT || x < L;
+        cjx[c] = xv ? fold(x - pxj, L) : 0;
+        cix[c] = xv ? fold(x - pxi, L) : 0;
+      }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int y = wid + NW * r;
+        const bool yv = EXACT || y < L;
+        const int ayj = yv ? fold(y - pyj, L) : 0, ayi = yv ? fold(y - pyi, L) : 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const R d = tab[ayj * H1 + cjx[c]] - tab[ayi * H1 + cix[c]];
+          E[r][c] = Energy<R>::add(E[r][c], d);
+          const bool ok = EXACT || (yv && lane + 64 * c < L);
+          R* dst = ok ? wr + (y * L + lane + 64 * c) : (R*)&sh->dummy;
+          *dst = E[r][c].x;
+        }
+      }
+      CG_MARK(tc3)
+    }
+
+    // R: evaluate against rd plus the pending hop's contribution to the lane's two sites
+    const uint64_t active = base + M - done;
+    int first = U, fi = 0, fj = 0, fdx = 0;
+    double fdh0 = 0.0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
+      const int i = ci[k], j = cj[k];
+      const uint32_t wi = occ[i >> 5], wj = occ[j >> 5];
+      R ei = rd[i], ej = rd[j];
+      const R td = tab[ct[k]];
+      uint32_t ni = (wi >> (i & 31)) & 1u, nj = (wj >> (j & 31)) & 1u;
+      if (pend) {
+        const int yi = row_of(i, magic), xi = i - yi * L;
+        const int yj = row_of(j, magic), xj = j - yj * L;
+        const R ci_ = tab[fold(yi - pyj, L) * H1 + fold(xi - pxj, L)] - tab[fold(yi - pyi, L) * H1 + fold(xi - pxi, L)];
+        const R cj_ = tab[fold(yj - pyj, L) * H1 + fold(xj - pxj, L)] - tab[fold(yj - pyi, L) * H1 + fold(xj - pxi, L)];
+        ei = ei + ci_;
+        ej = ej + cj_;
+        ni = i == pi ? 0u : (i == pj ? 1u : ni);
+        nj = j == pi ? 0u : (j == pj ? 1u : nj);
+      }
+      const bool th = (first == U) & (lab > done) & ((ni & (nj ^ 1u)) != 0u);
+      const R dh0 = (ej - ei) - td;
+      const R dH = dh0 - Ef * (R)cdx[k];
+      const bool acc = th & metropolis_nb(dH, cu[k], th, S);
+      theta_cnt += th ? 1u : 0u;
+      if (acc) {
+        first = k;
+        fi = i;
+        fj = j;
+        fdx = cdx[k];
+        fdh0 = (double)dh0;
+      }
+    }
+    const unsigned long long bal = __ballot(first < U);
+    if (bal != 0ull) {
+      const int wl = __ffsll(bal) - 1;
+      if (lane == wl) {
+        HopInfo h;
+        h.key = (uint32_t)(tid * U + first);
+        h.i = fi;
+        h.j = fj;
+        h.v = 0;
+        h.dH0 = fdh0;
+        h.pad[0] = fdx;
+        info[(it & 1) * kMaxWaves + wid] = h;
+        atomicMin(&sh->best[it % 3], ((uint64_t)h.key << 32) | ((uint64_t)fi << 16) | (uint64_t)fj);
+      }
+    }
+    if (tid == 0) sh->best[(it + 1) % 3] = ~0ull;
+    __syncthreads();
+    const uint64_t best = uni(sh->best[it % 3]);
+    const HopInfo* infr = info + (it & 1) * kMaxWaves;
+    ++it;
+    ++rounds;
+    evaluated += active;
+    if (pend) {
+      cur ^= 1;
+      pend = false;
+    }
+    CG_MARK(tc1)
+
+    if (best == ~0ull) {
+      done = base + M;
+      base = done;
+      cached = false;
+      if (done - scan0 >= ra.max_labels) {
+        status = -4;  // CG_ESTALL
+        break;
+      }
+      continue;
+    }
+
+    // X: the round's lowest accepted label becomes the pending hop
+    const uint32_t key = (uint32_t)(best >> 32);
+    const int hi = (int)((best >> 16) & 0xffffu), hj = (int)(best & 0xffffu);
+    double hdH0;
+    int hdx;
+    {
+      const HopInfo& w = infr[(key / U) >> 6];
+      hdH0 = uni(w.dH0);
+      hdx = uni(w.pad[0]);
+    }
+    const uint64_t q = base + 1 + (uint64_t)key;
+    const uint64_t m = q - s_last;
+    s_last = q;
+    done = q;
+    ++hops;
+    ++since;
+    P += hdx;
+    H0 = H0 + hdH0;
+    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    if (tid == 0) {
+      atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
+      atomicOr(&occ[hj >> 5], 1u << (hj & 31));
+      if (logged < S.log_cap) {
+        S.log_label[logged] = q;
+        S.log_from[logged] = hi;
+        S.log_to[logged] = hj;
+      }
+      if (ra.clock_mode != 0) sh->t = sh->t + gauss_dt(hops, m, sid, k0, k1, S.Gamma);
+    }
+    if (logged < S.log_cap) ++logged;
+    pend = true;
+    pi = hi;
+    pj = hj;
+    pyi = row_of(hi, magic);
+    pxi = hi - pyi * L;
+    pyj = row_of(hj, magic);
+    pxj = hj - pyj * L;
+    CG_MARK(tc2)
+    if (done == base + M) {
+      base = done;
+      cached = false;
+    }
+    if (hops >= target) break;
+    if (ra.K > 0 && since >= ra.K) break;
+    if (ra.time_mode) {
+      if (ra.clock_mode == 0) {
+        if (s_last >= s_end) break;
+      } else {
+        __syncthreads();  // the Gaussian clock is advanced by thread 0
+        if (uni(sh->t) >= t_end) break;
+      }
+    }
+  }
+
+  // the last hop's update (registers only: the values are not read again)
+  if (pend) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int x = lane + 64 * c;
+      const bool xv = EXACT || x < L;
+      const int cjx = xv ? fold(x - pxj, L) : 0, cix = xv ? fold(x - pxi, L) : 0;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int y = wid + NW * r;
+        const bool yv = EXACT || y < L;
+        const int ayj = yv ? fold(y - pyj, L) : 0, ayi = yv ? fold(y - pyi, L) : 0;
+        E[r][c] = Energy<R>::add(E[r][c], tab[ayj * H1 + cjx] - tab[ayi * H1 + cix]);
+      }
+    }
+  }
+  atomicAdd(&sh->theta, theta_cnt);
+  {
+    ET* __restrict__ g = (ET*)S.eps;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int y = wid + NW * r;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = lane + 64 * c;
+        if (y < L && x < L) g[y * L + x] = E[r][c];
+      }
+    }
+  }
+  __syncthreads();
   for (int k = tid; k < S.NW; k += 1024) S.occ[k] = occ[k];
   if (tid == 0) {
     gs->hops = hops;

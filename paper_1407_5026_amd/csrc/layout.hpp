@@ -111,7 +111,7 @@ __host__ __device__ inline HopLds hop_lds(int32_t N, int32_t NW, int32_t ntab, i
   o.orb = b;   b = align16(b + n_orb * 4);
   o.guide = b; b = align16(b + kGuideSize);
   o.ctrl = b;  b = align16(b + 96);
-  o.info = b;  b = align16(b + kMaxWaves * kInfoBytes);
+  o.info = b;  b = align16(b + 2 * kMaxWaves * kInfoBytes);
   o.total = b;
   return o;
 }

@@ -50,6 +50,8 @@ def compare_logs(sample, gpu_log, or_log, tol=1e-12):
     i, v, u = o.draw(s)
     p, dH = o.move(i, v)
     margin = abs(u - p)
+    # the first differing label must be a near-tie of the FP64 decision, or a label the
+    # oracle never reached in its log (both sides stop at the requested hop count)
     assert margin < tol, (f"hop {k}: gpu (label {gl[k]}, {gi[k]}->{gj[k]}) vs oracle (label {ol[k]}, "
                           f"{oi[k]}->{oj[k]}); at label {s} u={u!r} P_acc={p!r} dH={dH!r}")
     say(f"allowed flip at hop {k}: label {s} |u - P_acc| = {margin:.3g}")

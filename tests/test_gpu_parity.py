@@ -272,3 +272,39 @@ def test_autotune_returns_valid_choice():
     b = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, M=o.M, K_refresh=o.K_refresh)
     b.run_hops(3000)
     assert max(b.stats(k)["max_drift"] for k in range(len(samples))) <= 1e-5
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_fp32_matches_oracle_until_a_near_tie(variant):
+    """The FP32 form (either hop kernel) executes the oracle's hops until the first label whose
+    FP64 acceptance margin |u - P_acc| is below FP32 resolution (1e-4); that hop may differ."""
+    cg = require_gpu()
+    s = fp64_single(seed=17)[0]
+    hops = 3000
+    b = _batch(cg, [s], precision=cg.CG_FP32_REFRESH, K_refresh=1024, log_hops=hops, variant=variant)
+    b.run_hops(hops)
+    agree = compare_logs(s, b.hop_log(0), oracle_of(s).run(hops), tol=1e-4)
+    say(f"FP32 variant {variant}: {agree} of {hops} hops identical to the oracle")
+    assert agree >= 20
+
+
+def test_one_barrier_kernel_equals_two_barrier_kernel():
+    """Both FP32 hop kernels on a batch at L=128: identical hops until a near-tie."""
+    cg = require_gpu()
+    from workloads import headline
+
+    samples = headline(4)
+    hops = 600
+    b1 = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, log_hops=hops, variant=1)
+    b2 = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, log_hops=hops, variant=2)
+    b1.run_hops(hops)
+    b2.run_hops(hops)
+    for k, s in enumerate(samples):
+        l1, l2 = b1.hop_log(k), b2.hop_log(k)
+        n = min(len(l1[0]), len(l2[0]))
+        same = (l1[0][:n] == l2[0][:n]) & (l1[1][:n] == l2[1][:n]) & (l1[2][:n] == l2[2][:n])
+        first = n if same.all() else int(np.argmin(same))
+        say(f"sample {k}: kernels agree on {first} of {n} hops")
+        assert first >= 100
+        assert int(b2.occupation(k).sum()) == s.n_e
+        assert b2.stats(k)["max_drift"] <= 1e-5
