@@ -16,6 +16,8 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the hop kernels' LDS atomics come from single lanes: no wave-level reduction around them
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
 ]
 

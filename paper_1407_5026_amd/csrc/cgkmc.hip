@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "cgkmc.h"
+#include "hop_fx.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 
@@ -55,6 +56,8 @@ struct HostTables {
   std::vector<uint32_t> thr, orb;
   std::vector<int32_t> vec;
   std::vector<uint8_t> guide;
+  std::vector<uint16_t> guide16;  // kRaw: orbit | 0x8000 when a threshold lies inside the bucket
+  std::vector<int32_t> vec8;      // kRaw: [n_orb][8][2] member (dx, dy) packed, FP32 1/|d| bits
   std::vector<double> tab64;  // full folded table
   std::vector<double> tabk64;
   std::vector<float> tabk32;
@@ -123,6 +126,31 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
     while (o < n_orb - 1 && w >= (uint64_t)t.thr[o]) ++o;
     t.guide[k] = (uint8_t)o;
   }
+  if (layout == kRaw) {
+    // 16-bit guide: a bucket [w, w + 2^22) needs the threshold search only if some
+    // threshold of an orbit before the last lies strictly inside it
+    t.guide16.assign(kGuideSize, 0);
+    for (int32_t k = 0; k < kGuideSize; ++k) {
+      const uint64_t w = (uint64_t)k << (32 - kGuideBits), w_end = w + ((uint64_t)1 << (32 - kGuideBits));
+      const int32_t o = t.guide[k];
+      const bool inside = o < n_orb - 1 && (uint64_t)t.thr[o] < w_end;
+      t.guide16[k] = (uint16_t)(o | (inside ? 0x8000 : 0));
+    }
+    // 8 slots per orbit: member m & (size - 1) in slot m, so that slot w3 & 7 is member
+    // w3 & (size - 1) for sizes 4 and 8
+    t.vec8.assign((size_t)n_orb * 16, 0);
+    for (int32_t o = 0; o < n_orb; ++o) {
+      const int32_t first = (int32_t)(t.orb[o] & 0xffffu), msk = (int32_t)(t.orb[o] >> 16);
+      const double r = std::sqrt((double)reps[o].r2);
+      const float td = (float)(1.0 / r);
+      int32_t bits;
+      std::memcpy(&bits, &td, 4);
+      for (int32_t m = 0; m < 8; ++m) {
+        t.vec8[(size_t)(o * 8 + m) * 2] = t.vec[first + (m & msk)];
+        t.vec8[(size_t)(o * 8 + m) * 2 + 1] = bits;
+      }
+    }
+  }
   // 1/r by folded separation (|dy|, |dx|), minimum image, 1/r(0) := 0
   const int32_t H = L / 2, H1 = H + 1;
   t.H = H;
@@ -132,19 +160,29 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
       const int32_t r2 = ax * ax + ay * ay;
       t.tab64[(size_t)ay * H1 + ax] = r2 == 0 ? 0.0 : 1.0 / std::sqrt((double)r2);
     }
-  const size_t nk = layout == kTri ? (size_t)tri_entries(H) : (size_t)full_entries(H);
-  std::vector<double> k64(nk);
-  for (int32_t ay = 0; ay < H1; ++ay)
-    for (int32_t ax = 0; ax < H1; ++ax) {
-      size_t idx;
-      if (layout == kTri) {
-        const int32_t a = std::max(ay, ax), b = std::min(ay, ax);
-        idx = (size_t)(a * (a + 1) / 2 + b);
-      } else {
-        idx = (size_t)ay * H1 + ax;
-      }
-      k64[idx] = t.tab64[(size_t)ay * H1 + ax];
+  const size_t nk = layout == kTri ? (size_t)tri_entries(H)
+                    : layout == kRaw ? (size_t)fx_tab_entries(L) : (size_t)full_entries(H);
+  std::vector<double> k64(nk, 0.0);
+  if (layout == kRaw) {
+    // row b = dy + L, column u = folded |dx| (zero beyond L/2)
+    const int32_t Pp = fx_pitch(L);
+    for (int32_t b = 0; b < 2 * L; ++b) {
+      const int32_t a = std::abs(b - L), ay = std::min(a, L - a);
+      for (int32_t u = 0; u < H1; ++u) k64[(size_t)b * Pp + u] = t.tab64[(size_t)ay * H1 + u];
     }
+  } else {
+    for (int32_t ay = 0; ay < H1; ++ay)
+      for (int32_t ax = 0; ax < H1; ++ax) {
+        size_t idx;
+        if (layout == kTri) {
+          const int32_t a = std::max(ay, ax), b = std::min(ay, ax);
+          idx = (size_t)(a * (a + 1) / 2 + b);
+        } else {
+          idx = (size_t)ay * H1 + ax;
+        }
+        k64[idx] = t.tab64[(size_t)ay * H1 + ax];
+      }
+  }
   if (precision == CG_FP64) {
     t.tabk64 = std::move(k64);
   } else {
@@ -193,7 +231,7 @@ int32_t count_vectors(double rc) {
 
 // ---------------------------------------------------------------------------------
 struct SampleLayout {
-  size_t tab64, tabk, thr, orb, vec, guide, dft_tw, dft_T, static_end;  // uploaded in one copy
+  size_t tab64, tabk, thr, orb, vec, guide, vec8, guide16, dft_tw, dft_T, static_end;  // uploaded in one copy
   size_t eps, phi, occ, part, log_label, log_from, log_to, end;
   int32_t dft, dft_kc, dft_rows;
 };
@@ -201,7 +239,7 @@ struct SampleLayout {
 struct Plan {
   int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0, timers = 0;
   int32_t use_graph = 0, variant = 0;
-  bool use_db = false;
+  bool use_db = false, use_fx = false;
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
   uint64_t max_labels = 1ull << 32;
@@ -254,7 +292,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.timers = o->phase_timers;
   if (o->use_graph != 0 && o->use_graph != 1) return set_err(CG_EINVAL, "use_graph=%d", o->use_graph);
   p.use_graph = o->use_graph;
-  if (o->variant < 0 || o->variant > 2) return set_err(CG_EINVAL, "variant=%d", o->variant);
+  if (o->variant < 0 || o->variant > 3) return set_err(CG_EINVAL, "variant=%d", o->variant);
   p.variant = o->variant;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
@@ -298,12 +336,29 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     need_exact = std::max(need_exact, align16(NW * 4) + full_entries(H) * 8);
     max_N = std::max(max_N, N);
   }
-  // automatic choice: two barriers (measured faster at L = 128: 81e6 vs 75e6 hops/s)
+  // exact-geometry FP32 kernel: every sample has the same L, 64 or 128
+  bool same_L = true;
+  int32_t max_orb = 0;
+  for (int32_t b = 0; b < n; ++b) {
+    same_L = same_L && s[b].L == s[0].L;
+    max_orb = std::max(max_orb, count_orbits(s[b].rc));
+  }
+  const int32_t need_fx = fx_lds(s[0].L, max_orb).total;
+  const bool fx_ok = p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
+                     need_fx <= lds_cap;
+  p.use_fx = fx_ok && (p.variant == 0 || p.variant == 3);
+  if (p.variant == 3 && !p.use_fx)
+    return set_err(CG_EINVAL, "variant 3 (exact-geometry kernel) needs the FP32 form, one L in {64, 128} "
+                   "for all samples and %d bytes of LDS", need_fx);
+  // automatic choice otherwise: two barriers (measured faster at L = 128: 81e6 vs 75e6 hops/s)
   p.use_db = p.precision == CG_FP32_REFRESH && max_L_all <= 128 && db_fits && p.variant == 2;
   if (p.variant == 2 && !p.use_db)
     return set_err(CG_EINVAL, "variant 2 (one barrier per hop) needs the FP32 form, L <= 128 and %d bytes of LDS",
                    need_db);
-  if (p.use_db) {
+  if (p.use_fx) {
+    p.layout = kRaw;
+    p.lds_hop = need_fx;
+  } else if (p.use_db) {
     p.layout = kFull;
     p.lds_hop = need_db;
   } else if (full_fits) {
@@ -329,7 +384,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   for (int32_t b = 0; b < n; ++b) {
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
-    const int32_t ntab = p.layout == kTri ? tri_entries(H) : full_entries(H);
+    const int32_t ntab = p.layout == kTri ? tri_entries(H) : p.layout == kRaw ? fx_tab_entries(L) : full_entries(H);
     const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
     max_L = std::max(max_L, L);
     SampleLayout& q = p.sl[b];
@@ -346,12 +401,13 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     if (q.dft) p.lds_dft = std::max(p.lds_dft, fixed + kc * L * 24);
     else p.any_exact_refresh = true;
     q.tab64 = off;     off = align_up(off + (size_t)full_entries(H) * 8);
-    q.tabk = off;      off = align_up(off + (size_t)full_entries(H) * p.real_bytes);
-    (void)ntab;
+    q.tabk = off;      off = align_up(off + (size_t)ntab * p.real_bytes);
     q.thr = off;       off = align_up(off + (size_t)n_orb * 4);
     q.orb = off;       off = align_up(off + (size_t)n_orb * 4);
     q.vec = off;       off = align_up(off + (size_t)n_vec * 4);
     q.guide = off;     off = align_up(off + kGuideSize);
+    q.vec8 = off;      off = align_up(off + (p.layout == kRaw ? (size_t)n_orb * 64 : 0));
+    q.guide16 = off;   off = align_up(off + (p.layout == kRaw ? (size_t)kGuideSize * 2 : 0));
     q.dft_tw = off;    off = align_up(off + (size_t)L * 16);
     q.dft_T = off;     off = align_up(off + (size_t)(H + 1) * L * 8);
     q.static_end = off;
@@ -401,6 +457,10 @@ HopFn pick_db(int32_t U, int32_t NC, bool exact) {
 }
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db) {
+  if (layout == kRaw) {
+    if (NC == 1) return U == 1 ? k_hops_fx<64, 1> : k_hops_fx<64, 2>;
+    return U == 1 ? k_hops_fx<128, 1> : k_hops_fx<128, 2>;
+  }
   if (db) return pick_db(U, NC, exact);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
@@ -649,6 +709,10 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     std::memcpy(base + q.orb, t.orb.data(), t.orb.size() * 4);
     std::memcpy(base + q.vec, t.vec.data(), t.vec.size() * 4);
     std::memcpy(base + q.guide, t.guide.data(), t.guide.size());
+    if (p.layout == kRaw) {
+      std::memcpy(base + q.vec8, t.vec8.data(), t.vec8.size() * 4);
+      std::memcpy(base + q.guide16, t.guide16.data(), t.guide16.size() * 2);
+    }
     std::memcpy(base + q.dft_tw, t.dft_tw.data(), t.dft_tw.size() * 8);
     std::memcpy(base + q.dft_T, t.dft_T.data(), t.dft_T.size() * 8);
 
@@ -661,7 +725,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.NW = (N + 31) / 32;
     s.n_orb = t.n_orb;
     s.n_vec = t.n_vec;
-    s.ntab = p.layout == kTri ? tri_entries(t.H) : full_entries(t.H);
+    s.ntab = p.layout == kTri ? tri_entries(t.H) : p.layout == kRaw ? fx_tab_entries(L) : full_entries(t.H);
     s.nblk = (N + kInitBlock - 1) / kInitBlock;
     s.log_cap = p.log_cap;
     s.layout = p.layout;
@@ -680,6 +744,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.T32 = (float)d.T;
     s.E32 = (float)d.E;
     s.invT32 = (float)(1.0 / d.T);
+    s.mTln2_32 = (float)(-d.T * 0.6931471805599453);
     uint8_t* a = c->arena;
     s.st = (SampleState*)(a + p.states_off) + b;
     s.eps = a + q.eps;
@@ -691,6 +756,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.orb = (const uint32_t*)(a + q.orb);
     s.vec = (const int32_t*)(a + q.vec);
     s.guide = a + q.guide;
+    s.vec8 = (const int32_t*)(a + q.vec8);
+    s.guide16 = (const uint16_t*)(a + q.guide16);
     s.part = (double*)(a + q.part);
     s.dft_tw = (const double*)(a + q.dft_tw);
     s.dft_T = (const double*)(a + q.dft_T);
@@ -923,6 +990,7 @@ int cg_set_TE(cg_ctx* c, int32_t b, double T, double E) {
   s.T32 = (float)T;
   s.E32 = (float)E;
   s.invT32 = (float)(1.0 / T);
+  s.mTln2_32 = (float)(-T * 0.6931471805599453);
   HIPCHK(hipMemcpyAsync(c->d_samples + b, &s, sizeof(DevSample), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return CG_OK;

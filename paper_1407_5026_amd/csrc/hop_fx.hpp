@@ -1,0 +1,400 @@
+// hop_fx.hpp -- FP32 hop kernel for lattices that fill the 1024-thread geometry exactly
+// (L = 64 or 128; wave w owns rows w + 16 r, lane the columns lane + 64 c).
+//
+// It runs the same mixed parallel-rejection step as k_hops (section "Hopping conduction in
+// the Coulomb glass", steps 1, 2, 3a-3c, with the labels of a chunk drawn once and re-used
+// after a hop) and executes the same hops, with three changes in how the work is laid out:
+//
+//  * The 1/r table is indexed by the raw row difference b = dy + L in [1, 2L) and the folded
+//    column distance.  In step 3b a lane's table address for its row y = w + 16 r is then a
+//    per-hop base plus 16 r rows, a compile-time offset, so the row terms need neither
+//    scalar nor vector arithmetic.
+//  * A site's FP32 energy is a pair hi + lo.  Step 3b adds the FP32 increment
+//    1/r_lj - 1/r_li to lo, the proposals read fl(hi + lo) from LDS, and every kRenorm hops
+//    the pair is renormalised exactly (Fast2Sum) so that lo stays of the order of the recent
+//    increments: its rounding errors stay far below those of a single FP32 running sum, at
+//    three vector operations per site and hop.
+//  * Every label carries its LDS addresses and its acceptance threshold
+//    th = 1/r_ij + E dx - T ln u, so the test of Eq. 2, dH <= 0 or u < exp(-dH/T) with
+//    dH = eps_j - eps_i - 1/r_ij - E dx, is the single comparison eps_j - eps_i <= th
+//    (the two forms agree up to FP32 rounding of th).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace cg {
+
+// One cached label: sites, LDS byte addresses of their energies and occupation words,
+// displacement dx, acceptance threshold and 1/r_ij.
+struct FxLabel {
+  int32_t i, j, dx;
+  uint32_t ai, aj, oi, oj;
+  float th, td;
+};
+
+struct FxShared {
+  uint32_t mask[3];  // per-round bitmask of waves holding an accepted label (triple-buffered)
+  uint32_t theta;
+  double t;          // Gaussian clock
+};
+
+template <int L>
+struct FxGeo {
+  static constexpr int LG = L == 64 ? 6 : 7;
+  static constexpr int N = L * L;
+  static constexpr int NC = L / 64;
+  static constexpr int RPW = L / 16;
+  static constexpr int P = fx_pitch(L);
+  static_assert(L == 64 || L == 128, "exact geometry: L = 64 or 128");
+};
+
+// LDS accesses by 32-bit local address.  The dynamic LDS base is added once where an
+// address is formed, so a load or store costs no address arithmetic of its own and a
+// constant offset lands in the instruction's offset field.
+template <typename T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+
+__device__ __forceinline__ uint32_t lds_addr_of(const uint8_t* p) {
+  return (uint32_t)(uintptr_t)(lds_ptr<const uint8_t>)p;
+}
+template <typename T>
+__device__ __forceinline__ T lds_ld(uint32_t a) {
+  return *(lds_ptr<const T>)a;
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(uint32_t a, T v) {
+  *(lds_ptr<T>)a = v;
+}
+// Keeps a per-lane address opaque so that constant offsets added to it are not merged
+// into a wave-uniform part of its computation.
+__device__ __forceinline__ uint32_t opaque(uint32_t a) {
+  asm volatile("" : "+v"(a));
+  return a;
+}
+
+// Folded column distance min(|x - x0|, L - |x - x0|) for x, x0 in [0, L), L a power of two.
+template <int L>
+__device__ __forceinline__ int fold_col(int x, int x0) {
+  const int d = (x - x0) & (L - 1);
+  const int e = L - d;
+  return d < e ? d : e;
+}
+
+// Step 1 for this lane's labels of the chunk starting after `base`: Philox4x32-10 of
+// (label, sample, PROPOSE); site i = mulhi(w0, N) = w0 >> (32 - log2 N); orbit from the
+// 16-bit guide (searched through the thresholds only when the bucket holds one); member
+// w3 & (size - 1), read as w3 & 7 from the 8-slot table; acceptance uniform
+// (2 (w2 >> 9) + 1) 2^-24.
+template <int L, int U>
+__device__ __forceinline__ void draw_fx(uint64_t base, int tid, const DevSample& S, uint32_t lds0,
+                                        const FxLds& lo, float Ef, float mTln2, FxLabel (&lb)[U]) {
+  using G = FxGeo<L>;
+  const uint32_t guide = lds0 + lo.guide, thr = lds0 + lo.thr, vec8 = lds0 + lo.vec8;
+  const uint32_t ev = lds0 + lo.ev, occ = lds0 + lo.occ;
+  const int last = S.n_orb - 1;
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
+    uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = S.sample_id, c3 = kTagPropose;
+    philox10(c0, c1, c2, c3, S.seed_lo, S.seed_hi);
+    const int i = (int)(c0 >> (32 - 2 * G::LG));
+    const uint32_t g = lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuideBits)));
+    int o = (int)(g & 0x7fffu);
+    if (g & 0x8000u) {
+      while (o < last && c1 >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
+    }
+    const uint64_t v = lds_ld<uint64_t>(vec8 + 8 * (o * 8 + (int)(c3 & 7u)));
+    const int vx = (int)(uint32_t)v;
+    const int dx = (int)(int16_t)(vx & 0xffff), dy = vx >> 16;
+    const int xi = i & (L - 1), yi = i >> G::LG;
+    const int j = (((yi + dy) & (L - 1)) << G::LG) | ((xi + dx) & (L - 1));
+    const float td = __uint_as_float((uint32_t)(v >> 32));
+    const float u = (float)(2u * (c2 >> 9) + 1u) * 0x1p-24f;
+    FxLabel& b = lb[k];
+    b.i = i;
+    b.j = j;
+    b.ai = ev + 4 * i;
+    b.aj = ev + 4 * j;
+    b.oi = occ + 4 * (i >> 5);
+    b.oj = occ + 4 * (j >> 5);
+    b.dx = dx;
+    b.td = td;
+    b.th = (td + Ef * (float)dx) + mTln2 * __log2f(u);
+  }
+}
+
+template <int L, int U>
+__global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ samples,
+                                                  const int32_t* __restrict__ order, RunArgs ra) {
+  using G = FxGeo<L>;
+  constexpr int NW = 16, NC = G::NC, RPW = G::RPW, P = G::P;
+  constexpr uint32_t M = 1024u * U;
+  constexpr int kRenorm = 16;
+  const DevSample& S = samples[order[blockIdx.x]];
+  SampleState* __restrict__ gs = S.st;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = uni((int32_t)(tid >> 6));
+
+  uint64_t hops = uni(gs->hops);
+  uint64_t s_last = uni(gs->s_last);
+  int32_t since = uni(gs->since_refresh);
+  const uint64_t target = uni(gs->hop_target);
+  const uint64_t scan0 = uni(gs->call_scan0);
+  const double t_end = uni(gs->t_end);
+  const double t_start = uni(gs->t);
+  {
+    const bool idle = uni(gs->status) != 0 || hops >= target || (ra.time_mode && t_start >= t_end) ||
+                      (ra.K > 0 && since >= ra.K);
+    if (idle) return;
+  }
+  uint64_t base = uni(gs->s_scan);  // labels base + 1 .. base + M form the current chunk
+  uint32_t dpos = 0;                // labels up to base + dpos are decided
+  int64_t P_ = uni(gs->P);
+  double H0 = uni(gs->H0);
+  uint64_t sum_p = uni(gs->sum_p), rounds = uni(gs->rounds), evaluated = uni(gs->evaluated);
+  int64_t logged = uni(gs->logged);
+  int32_t status = 0;
+
+  extern __shared__ __align__(16) uint8_t smem[];
+  const FxLds lo = fx_lds(L, S.n_orb);
+  const uint32_t lds0 = lds_addr_of(smem);
+  float* __restrict__ ev = (float*)(smem + lo.ev);
+  uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
+  FxShared* __restrict__ sh = (FxShared*)(smem + lo.ctrl);
+  uint4* __restrict__ info = (uint4*)(smem + lo.info);
+
+  // owned energies (hi, lo) in registers, fl(hi + lo) in LDS
+  float eh[RPW][NC], el[RPW][NC];
+  {
+    const float2* __restrict__ g = (const float2*)S.eps;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int l = (wid + NW * r) * L + lane + 64 * c;
+        const float2 e = g[l];
+        eh[r][c] = e.x;
+        el[r][c] = e.y;
+        ev[l] = e.x + e.y;
+      }
+    }
+    const uint4* __restrict__ gt = (const uint4*)S.tabk;
+    uint4* __restrict__ st = (uint4*)(smem + lo.tab);
+    for (int k = tid; k < fx_tab_entries(L) / 4; k += 1024) st[k] = gt[k];
+  }
+  for (int k = tid; k < G::N / 32; k += 1024) occ[k] = S.occ[k];
+  for (int k = tid; k < S.n_orb; k += 1024) ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
+  for (int k = tid; k < kGuideSize; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
+  for (int k = tid; k < S.n_orb * 8; k += 1024) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
+  if (tid == 0) {
+    sh->mask[0] = sh->mask[1] = sh->mask[2] = 0u;
+    sh->theta = 0u;
+    sh->t = t_start;
+  }
+  __syncthreads();
+
+  const uint32_t k0 = S.seed_lo, k1 = S.seed_hi, sid = S.sample_id;
+  const uint64_t s_end = uni((ra.time_mode && ra.clock_mode == 0) ? label_at_time(t_end, S.Gamma) : (uint64_t)0);
+  const float Ef = S.E32, mTln2 = S.mTln2_32;
+  // this lane's energy value of row wid + 16 r, column lane + 64 c is at ev_lane + r kRowEv + 256 c
+  const uint32_t ev_lane = opaque(lds0 + lo.ev + 4 * (uint32_t)(wid * L + lane));
+  constexpr int kRowEv = NW * L * 4, kRowTab = NW * P * 4;
+  bool cached = false;
+  FxLabel lb[U];
+  uint32_t theta_cnt = 0;
+  uint32_t slot = 0;
+  uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
+  const bool timers = ra.timers != 0;
+#define CG_MARK(acc)                                          \
+  if (timers) {                                               \
+    const uint64_t now_ = __builtin_amdgcn_s_memtime();       \
+    acc += now_ - tmark;                                      \
+    tmark = now_;                                             \
+  }
+  if (timers) tmark = __builtin_amdgcn_s_memtime();
+
+  // one iteration per executed hop; the energies change only in its straight-line part
+  for (;;) {
+    // rounds until a round accepts a label (or the label cap stops the sample)
+    uint32_t mk = 0u;
+    for (;;) {
+    if (!cached) {
+      draw_fx<L, U>(base, tid, S, lds0, lo, Ef, mTln2, lb);
+      cached = true;
+      CG_MARK(tc0)
+    }
+
+    // step 2 for the undecided labels: occupancy filter and Metropolis; the lane keeps its
+    // first accepted label
+    int first = U;
+    uint32_t pub0 = 0u, pub1 = 0u;
+    float pdh = 0.f;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const FxLabel& b = lb[k];
+      const uint32_t key = (uint32_t)(tid * U + k);
+      const uint32_t wi = lds_ld<uint32_t>(b.oi), wj = lds_ld<uint32_t>(b.oj);
+      const float ei = lds_ld<float>(b.ai), ej = lds_ld<float>(b.aj);
+      const float de = ej - ei;
+      const bool th = (first == U) & (key >= dpos) & ((((wi >> (b.i & 31)) & ~(wj >> (b.j & 31))) & 1u) != 0u);
+      const bool acc = th & (de <= b.th);
+      theta_cnt += th ? 1u : 0u;
+      if (acc) {
+        first = k;
+        pub0 = (uint32_t)b.i | ((uint32_t)b.j << 16);
+        pub1 = key | ((uint32_t)b.dx << 16);
+        pdh = de - b.td;
+      }
+    }
+    // the wave's lowest accepting lane publishes its label; the round's winner is the
+    // lowest wave with an accepted label (keys grow with the thread index)
+    const uint32_t nxt = slot == 2u ? 0u : slot + 1u;
+    const unsigned long long bal = __ballot(first < U);
+    if (bal != 0ull) {
+      if (lane == __ffsll(bal) - 1) {
+        info[wid] = make_uint4(pub0, pub1, __float_as_uint(pdh), 0u);
+        atomicOr(&sh->mask[slot], 1u << wid);
+      }
+    }
+    if (tid == 0) sh->mask[nxt] = 0u;
+    __syncthreads();
+    mk = uni(sh->mask[slot]);
+    slot = nxt;
+    ++rounds;
+    evaluated += M - dpos;
+    CG_MARK(tc1)
+    if (mk != 0u) break;
+    // every label of the chunk is rejected
+    base += M;
+    dpos = 0;
+    cached = false;
+    if (base - scan0 >= ra.max_labels) {
+      status = -4;  // CG_ESTALL
+      break;
+    }
+    }
+    if (mk == 0u) break;
+
+    // step 3: execute the lowest accepted label
+    const uint4 w = info[__ffs(mk) - 1];
+    const uint32_t w0 = uni(w.x), w1 = uni(w.y);
+    const float dh0 = __uint_as_float(uni(w.z));
+    const int hi = (int)(w0 & 0xffffu), hj = (int)(w0 >> 16);
+    const uint32_t key = w1 & 0xffffu;
+    const int hdx = (int)w1 >> 16;
+    const uint64_t q = base + 1 + key;
+    const uint64_t m = q - s_last;
+    s_last = q;
+    dpos = key + 1;
+    ++hops;
+    ++since;
+    P_ += hdx;
+    H0 = H0 + (double)dh0;
+    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    if (tid == 0) {
+      atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
+      atomicOr(&occ[hj >> 5], 1u << (hj & 31));
+      if (logged < S.log_cap) {
+        S.log_label[logged] = q;
+        S.log_from[logged] = hi;
+        S.log_to[logged] = hj;
+      }
+      if (ra.clock_mode != 0) sh->t = sh->t + gauss_dt(hops, m, sid, k0, k1, S.Gamma);
+    }
+    if (logged < S.log_cap) ++logged;
+    CG_MARK(tc2)
+
+    // step 3b on the owned sites: lo += 1/r_lj - 1/r_li, LDS value fl(hi + lo).  Row
+    // y = wid + 16 r of the table for origin row y0 is row wid - y0 + L + 16 r.  All table
+    // loads are issued before the first store.
+    {
+      const int xi = hi & (L - 1), yi = hi >> G::LG, xj = hj & (L - 1), yj = hj >> G::LG;
+      const uint32_t rj = lds0 + lo.tab + (uint32_t)((wid - yj + L) * P * 4);
+      const uint32_t ri = lds0 + lo.tab + (uint32_t)((wid - yi + L) * P * 4);
+      uint32_t aj[NC], ai[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = lane + 64 * c;
+        aj[c] = opaque(rj + 4 * (uint32_t)fold_col<L>(x, xj));
+        ai[c] = opaque(ri + 4 * (uint32_t)fold_col<L>(x, xi));
+      }
+      float d[RPW][NC];
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          d[r][c] = lds_ld<float>(aj[c] + r * kRowTab) - lds_ld<float>(ai[c] + r * kRowTab);
+      }
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          el[r][c] = el[r][c] + d[r][c];
+          lds_st<float>(ev_lane + r * kRowEv + 256 * c, eh[r][c] + el[r][c]);
+        }
+      }
+      if ((hops & (uint64_t)(kRenorm - 1)) == 0) {
+        // Fast2Sum: z = fl(hi + lo) - hi is exact and hi + z = fl(hi + lo), so the pair
+        // keeps its sum while hi absorbs lo (written as updates of hi and lo in place)
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            const float z = (eh[r][c] + el[r][c]) - eh[r][c];
+            el[r][c] = el[r][c] - z;
+            eh[r][c] = eh[r][c] + z;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    CG_MARK(tc3)
+    if (dpos == M) {
+      base += M;
+      dpos = 0;
+      cached = false;
+    }
+    if (hops >= target) break;
+    if (ra.time_mode) {
+      if (ra.clock_mode == 0 ? s_last >= s_end : uni(sh->t) >= t_end) break;
+    }
+    if (ra.K > 0 && since >= ra.K) break;
+  }
+
+  atomicAdd(&sh->theta, theta_cnt);
+  {
+    float2* __restrict__ g = (float2*)S.eps;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) g[(wid + NW * r) * L + lane + 64 * c] = make_float2(eh[r][c], el[r][c]);
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < G::N / 32; k += 1024) S.occ[k] = occ[k];
+  if (tid == 0) {
+    gs->hops = hops;
+    gs->s_last = s_last;
+    gs->s_scan = base + dpos;
+    gs->P = P_;
+    gs->t = ra.clock_mode == 0 ? (double)s_last / S.Gamma : sh->t;
+    gs->H0 = H0;
+    gs->since_refresh = since;
+    gs->status = status;
+    gs->sum_p = sum_p;
+    gs->rounds = rounds;
+    gs->evaluated = evaluated;
+    gs->theta_pass += sh->theta;
+    gs->logged = logged;
+    if (timers) {
+      gs->phase_cycles[0] += tc0;
+      gs->phase_cycles[1] += tc1;
+      gs->phase_cycles[2] += tc2;
+      gs->phase_cycles[3] += tc3;
+    }
+  }
+#undef CG_MARK
+}
+
+}  // namespace cg

@@ -130,12 +130,15 @@ template <typename R> struct Energy;
 template <> struct Energy<double> {
   using T = double;
   __device__ static double value(T e) { return e; }
+  __device__ static double total(T e) { return e; }
   __device__ static T add(T e, double d) { return e + d; }
   __device__ static T from64(double v) { return v; }
 };
 template <> struct Energy<float> {
   using T = float2;
   __device__ static float value(T e) { return e.x; }
+  // the energy the pair represents (value + low part, exact in FP64)
+  __device__ static double total(T e) { return (double)e.x + (double)e.y; }
   __device__ static T add(T e, float d) {
     const float y = d + e.y;
     const float t = e.x + y;
@@ -993,7 +996,7 @@ __global__ void __launch_bounds__(kInitBlock) k_eps_exact(const DevSample* __res
       }
     }
     typename Energy<R>::T* e = (typename Energy<R>::T*)S.eps;
-    if (refresh) drift = fabs((double)Energy<R>::value(e[l]) - acc);
+    if (refresh) drift = fabs(Energy<R>::total(e[l]) - acc);
     e[l] = Energy<R>::from64(acc);
     const bool nl = (occ[l >> 5] >> (l & 31)) & 1u;
     const double ph = S.phi[l];
@@ -1141,7 +1144,7 @@ __global__ void __launch_bounds__(1024) k_refresh_dft(const DevSample* __restric
         const int l = y * L + x;
         const double ph = S.phi[l];
         const double e64 = ph + acc[r] * invL;
-        dmax = fmax(dmax, fabs((double)Energy<R>::value(e[l]) - e64));
+        dmax = fmax(dmax, fabs(Energy<R>::total(e[l]) - e64));
         e[l] = Energy<R>::from64(e64);
         const bool nl = (occ[l >> 5] >> (l & 31)) & 1u;
         hsum = hsum + ((nl ? ph : 0.0) + 0.5 * ((nl ? q1 : q0) * (e64 - ph)));

@@ -12,6 +12,7 @@
 //   vec   [n_vec] i32                    member displacement (dx & 0xffff) | dy << 16
 //   guide [1024] u8                      orbit at the start of each 2^22-wide bucket of w1
 //   dft_tw [L] double2, dft_T [(H+1) L] double   twiddles and transformed 1/r for the refresh
+//   vec8  [n_orb][8] int2, guide16 [1024] u16   proposal tables of the exact-geometry kernel
 //   part  [2 * nblk] double              per-block partial sums (energy, drift)
 //   log   [cap] u64 + 2 x [cap] i32      executed-hop log (label, from, to)
 #pragma once
@@ -26,7 +27,9 @@ constexpr int kMaxWaves = 16;       // 1024 threads of 64 lanes
 constexpr int kMaxCols = 4;         // columns per lane in the row update: L <= 256
 constexpr int kInitBlock = 256;     // threads per block of the init / refresh kernels
 
-enum TableLayout : int32_t { kFull = 0, kTri = 1 };
+// kFull: (H+1)^2 table by (|dy|, |dx|); kTri: its triangle |dx| <= |dy|; kRaw: the exact-geometry
+// FP32 kernel's table by raw row difference dy + L and folded column distance (see fx_pitch).
+enum TableLayout : int32_t { kFull = 0, kTri = 1, kRaw = 2 };
 
 struct SampleState {
   uint64_t s_last;        // label of the last executed hop
@@ -60,7 +63,7 @@ struct DevSample {
   int32_t dft_kc, dft_rows, pad2_[2];   // frequencies per LDS chunk, outputs per thread
   uint32_t seed_lo, seed_hi, sample_id, magic_L;  // magic_L = ceil(2^32 / L)
   double nu, W, T, E, Gamma;
-  float T32, E32, invT32, pad32_;
+  float T32, E32, invT32, mTln2_32;  // mTln2_32 = -T ln 2 (acceptance thresholds)
   SampleState* st;
   void* eps;
   double* phi;
@@ -71,6 +74,8 @@ struct DevSample {
   const uint32_t* orb;
   const int32_t* vec;
   const uint8_t* guide;
+  const int32_t* vec8;    // kRaw: [n_orb][8] (dx & 0xffff | dy << 16, bits of FP32 1/|d|)
+  const uint16_t* guide16;  // kRaw: orbit at each bucket start | 0x8000 if a threshold lies inside
   double* part;
   const double* dft_tw;   // [L] (cos, sin)(2 pi j / L)
   const double* dft_T;    // [(H+1) x L] sum_dx T(dx, dy) cos(2 pi k dx / L), row k
@@ -112,6 +117,35 @@ __host__ __device__ inline HopLds hop_lds(int32_t N, int32_t NW, int32_t ntab, i
   o.guide = b; b = align16(b + kGuideSize);
   o.ctrl = b;  b = align16(b + 96);
   o.info = b;  b = align16(b + 2 * kMaxWaves * kInfoBytes);
+  o.total = b;
+  return o;
+}
+
+// Exact-geometry FP32 kernel (L = 64 or 128, every thread owns L*L/1024 sites).
+// Its 1/r table holds row b in [0, 2L) for the raw row difference dy = b - L and column u
+// for the folded column distance u <= L/2: entry 1/sqrt(fold(b - L)^2 + u^2), 0 at the
+// origin and beyond u = L/2.  The row pitch is a multiple of 4 floats so that a wave's
+// rows, 16 apart, are a multiple of 256 bytes apart.
+__host__ __device__ constexpr int32_t fx_pitch(int32_t L) { return ((L / 2 + 1) + 3) & ~3; }
+__host__ __device__ constexpr int32_t fx_tab_entries(int32_t L) { return 2 * L * fx_pitch(L); }
+
+struct FxLds {
+  int32_t ev, occ, tab, thr, guide, ctrl, info, vec8, total;
+};
+
+// LDS of the exact-geometry kernel: energy values, occupation, table, thresholds, guide,
+// control words, per-wave winner records, displacement table.
+__host__ __device__ inline FxLds fx_lds(int32_t L, int32_t n_orb) {
+  FxLds o;
+  int32_t b = 0;
+  o.ev = b;    b = align16(b + L * L * 4);
+  o.occ = b;   b = align16(b + L * L / 8);
+  o.tab = b;   b = align16(b + fx_tab_entries(L) * 4);
+  o.thr = b;   b = align16(b + n_orb * 4);
+  o.guide = b; b = align16(b + kGuideSize * 2);
+  o.ctrl = b;  b = align16(b + 64);
+  o.info = b;  b = align16(b + kMaxWaves * 16);
+  o.vec8 = b;  b = align16(b + n_orb * 64);
   o.total = b;
   return o;
 }

@@ -274,29 +274,39 @@ def test_autotune_returns_valid_choice():
     assert max(b.stats(k)["max_drift"] for k in range(len(samples))) <= 1e-5
 
 
-@pytest.mark.parametrize("variant", [1, 2])
-def test_fp32_matches_oracle_until_a_near_tie(variant):
-    """The FP32 form (either hop kernel) executes the oracle's hops until the first label whose
-    FP64 acceptance margin |u - P_acc| is below FP32 resolution (1e-4); that hop may differ."""
+@pytest.mark.parametrize("variant,L,M", [(1, 64, 1024), (2, 64, 1024), (3, 64, 1024), (3, 64, 2048),
+                                        (3, 128, 1024), (3, 128, 2048)])
+def test_fp32_matches_oracle_until_a_near_tie(variant, L, M):
+    """The FP32 form (each hop kernel: 1 two-barrier, 2 one-barrier, 3 exact-geometry) executes
+    the oracle's hops until the first label whose FP64 acceptance margin |u - P_acc| is below
+    FP32 resolution (1e-4); that hop may differ."""
     cg = require_gpu()
-    s = fp64_single(seed=17)[0]
+    if L == 64:
+        s = fp64_single(seed=17)[0]
+    else:
+        from workloads import headline
+
+        s = headline(1, seed=23)[0]
     hops = 3000
-    b = _batch(cg, [s], precision=cg.CG_FP32_REFRESH, K_refresh=1024, log_hops=hops, variant=variant)
+    b = _batch(cg, [s], precision=cg.CG_FP32_REFRESH, M=M, K_refresh=1024, log_hops=hops, variant=variant)
     b.run_hops(hops)
     agree = compare_logs(s, b.hop_log(0), oracle_of(s).run(hops), tol=1e-4)
-    say(f"FP32 variant {variant}: {agree} of {hops} hops identical to the oracle")
+    say(f"FP32 variant {variant} L={L} M={M}: {agree} of {hops} hops identical to the oracle")
     assert agree >= 20
+    assert b.stats(0)["max_drift"] <= 1e-5
 
 
-def test_one_barrier_kernel_equals_two_barrier_kernel():
-    """Both FP32 hop kernels on a batch at L=128: identical hops until a near-tie."""
+@pytest.mark.parametrize("other", [2, 3])
+def test_fp32_kernels_agree(other):
+    """The FP32 hop kernels on a batch at L=128 against the two-barrier kernel: identical hops
+    until a near-tie."""
     cg = require_gpu()
     from workloads import headline
 
     samples = headline(4)
     hops = 600
     b1 = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, log_hops=hops, variant=1)
-    b2 = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, log_hops=hops, variant=2)
+    b2 = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, log_hops=hops, variant=other)
     b1.run_hops(hops)
     b2.run_hops(hops)
     for k, s in enumerate(samples):
