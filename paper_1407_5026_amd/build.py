@@ -8,6 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "cgkmc.hip")
 LIB = os.path.join(HERE, "libcgkmc.so")
+PROBE_SRC = os.path.join(HERE, "csrc", "lds_probe.hip")
+PROBE = os.path.join(HERE, "lds_probe")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -34,5 +36,20 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_probe(verbose: bool = False) -> str:
+    """The unit-throughput probe behind the roofline denominators (a standalone program)."""
+    tmp = PROBE + ".tmp"
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    cmd = [HIPCC, *flags, "-o", tmp, PROBE_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stderr[-6000:]}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))
