@@ -25,17 +25,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 256 CUs x 128 B/clk x 2.4 GHz: LDS bandwidth of the chip (see the measurement notes)
-LDS_PEAK_GBS = 256 * 128 * 2.4
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hops_l128_batch256_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1407_5026_amd", "csrc", "kernels.hpp")
+# LDS bandwidth of the chip: 256 CUs x 224 B/clk x 2.4 GHz, the best rate the unit probe
+# (python -m paper_1407_5026_amd.probe) measures on MI355X, with 16-byte ds_read_b128; 4-byte
+# reads reach 65 B/clk and 4-byte writes 52 B/clk, because each LDS instruction occupies the
+# CU's LDS pipe for ~4-5 cycles whatever its width
+LDS_PEAK_GBS = 256 * 224 * 2.4
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hops_fx_l128_b256_traffic.json")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1407_5026_amd", "csrc", f) for f in ("hop_fx.hpp", "kernels.hpp", "layout.hpp")]
 
 
 def kernel_hash() -> str:
+    """Hash of the hop kernel's sources: a traffic record applies only to the code it measured."""
     import hashlib
 
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -56,26 +63,31 @@ def _cpu_worker(args):
     import oracle
     from workloads import headline
 
-    b, hops, seed = args
+    b, warm, hops, seed = args
     s = headline(b + 1, seed=seed)[b]
     o = oracle.Oracle(L=s.L, n_e=s.n_e, W=s.W, xi=s.xi, rc=s.rc, T=s.T, E=s.E, seed=s.seed,
                       sample_id=s.sample_id)
+    if warm:
+        o.run(warm, log_cap=0)
     t0 = time.perf_counter()
     o.run(hops, log_cap=0)
     return hops, time.perf_counter() - t0
 
 
-def cpu_baseline(hops: int, seed: int, cores: int) -> dict:
-    """The serial FP64 oracle on this host: one headline sample per process, `hops` hops
-    each from the random start, all processes concurrently; aggregate = sum of rates."""
+def cpu_baseline(warm: int, hops: int, seed: int, cores: int) -> dict:
+    """The serial FP64 oracle on this host: one headline sample per process, `warm` untimed hops
+    from the random start (the GPU's warmup window), then `hops` timed hops; all processes run
+    concurrently and the aggregate is the sum of their rates."""
     import multiprocessing as mp
 
     with mp.get_context("fork").Pool(cores) as pool:
-        res = pool.map(_cpu_worker, [(b, hops, seed) for b in range(cores)])
+        res = pool.map(_cpu_worker, [(b, warm, hops, seed) for b in range(cores)])
     rate = sum(h / t for h, t in res)
+    cpu_s = sum(t for _, t in res)
     return {"value": rate, "unit": "accepted hops/s", "cores": cores, "kind": "oracle",
-            "sample": f"serial FP64 oracle, L=128 T=0.02 E=0.005 rc=10, samples 0..{cores - 1}, "
-                      f"{hops} hops each from the random start, {cores} processes, rates summed"}
+            "sample": f"serial FP64 oracle, L=128 T=0.02 E=0.005 rc=10, samples 0..{cores - 1}: "
+                      f"hops {warm}..{warm + hops} of each sample timed after {warm} untimed hops from "
+                      f"the random start, {cores} processes, rates summed ({cpu_s:.1f} s of CPU time)"}
 
 
 def run_form(cg, torch, samples, precision, args, hops_per_step):
@@ -87,12 +99,26 @@ def run_form(cg, torch, samples, precision, args, hops_per_step):
     torch.cuda.synchronize()
     before = [b.stats(k) for k in range(n)]
     b.kernel_time()  # reset the event accumulators
+    # window boundaries: events on the library's stream, read after the timed region
+    per_win = max(1, args.window_hops // hops_per_step)
+    marks = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
+        if k % per_win == 0:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(b.stream)
+            marks.append((k, e))
         b.run_hops(hops_per_step)
+    e = torch.cuda.Event(enable_timing=True)
+    e.record(b.stream)
+    marks.append((args.steps, e))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    windows = []
+    for (k0, e0), (k1, e1) in zip(marks, marks[1:]):
+        ms = e0.elapsed_time(e1)
+        windows.append(n * hops_per_step * (k1 - k0) / (ms * 1e-3))
     hop_ms, hop_n, ref_ms, ref_n = b.kernel_time()
     after = [b.stats(k) for k in range(n)]
     hops = sum(a["hops"] - c["hops"] for a, c in zip(after, before))
@@ -102,23 +128,58 @@ def run_form(cg, torch, samples, precision, args, hops_per_step):
     drift = max(a["max_drift"] for a in after)
     b.close()
     return dict(seconds=dt, hops=hops, proposals=props, evaluated=evald, theta=theta, hop_ms=hop_ms,
-                hop_launches=hop_n, refresh_ms=ref_ms, refresh_launches=ref_n, max_drift=drift)
+                hop_launches=hop_n, refresh_ms=ref_ms, refresh_launches=ref_n, max_drift=drift,
+                windows=windows, window_hops=per_win * hops_per_step)
+
+
+def large_lattice(cg, torch, L: int, hops: int, warm: int) -> dict:
+    """One sample of side L on the whole GPU (FP64 form): the paper's large-lattice setting
+    (nu = 1/2, xi = 1, W = 1, T = 0.05, E = T/10; hop cutoff rc = 10), warm untimed hops from
+    the random start, then `hops` timed hops."""
+    from workloads import Sample
+
+    s = Sample(L, L * L // 2, 1.0, 1.0, 10.0, 0.05, 0.005, 7, 0)
+    t0 = time.perf_counter()
+    b = cg.Batch([s], cg.make_opts(precision=cg.CG_FP64))
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    if warm:
+        b.run_hops(warm)
+    torch.cuda.synchronize()
+    st0 = b.stats(0)
+    b.kernel_time()
+    t0 = time.perf_counter()
+    b.run_hops(hops)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st1 = b.stats(0)
+    m_bar = (st1["s_last"] - st0["s_last"]) / max(st1["hops"] - st0["hops"], 1)
+    b.close()
+    return {"L": L, "N": L * L, "T": 0.05, "E": 0.005, "hops": hops, "warmup_hops": warm, "hops_per_s": hops / dt,
+            "us_per_hop": dt / hops * 1e6, "m_bar": m_bar, "init_s": init_s,
+            "paper_gpu_ms_per_hop_T005": {"64": 0.10, "2048": 1.04}.get(str(L))}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    # default: 10^6 accepted hops per sample from the random start (one untimed step of 4096
+    # hops, then 244 timed steps), reported whole-run and per window of ~10^5 hops
+    ap.add_argument("--steps", type=int, default=244)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--window-hops", type=int, default=98304)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--hops-per-step", type=int, default=4096)
     ap.add_argument("--M", type=int, default=1024)
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--skip-fp64", action="store_true")
-    ap.add_argument("--cpu-hops", type=int, default=3000)
+    ap.add_argument("--cpu-hops", type=int, default=8192)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--large-L", type=int, default=0,
+                    help="also time one sample of this side (a power of two, 256..2048) on the whole GPU, FP64")
+    ap.add_argument("--large-hops", type=int, default=2000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB with a plain device copy (a counter "
                          "calibration point for FETCH_SIZE / WRITE_SIZE runs)")
@@ -180,25 +241,32 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.batch} samples L=128 N=16384 half filling W=1 xi=1 rc=10 "
-                               f"T=0.02 E=0.005, {args.hops_per_step} hops per sample per step, "
-                               f"FP32 with FP64 refresh every {args.K} hops",
+                               f"T=0.02 E=0.005 from the random start: {args.warmup * args.hops_per_step} "
+                               f"untimed then {args.steps * args.hops_per_step} timed accepted hops per "
+                               f"sample in steps of {args.hops_per_step}, FP32 with FP64 refresh every "
+                               f"{args.K} hops",
                    "batch": args.batch, "L": 128, "M": args.M, "block": args.block,
                    "K_refresh": args.K, "hops_per_step": args.hops_per_step},
         "proposals_per_s": r32["proposals"] / r32["seconds"],
         "evaluated_labels_per_s": r32["evaluated"] / r32["seconds"],
         "fp32_max_drift": r32["max_drift"],
         "refresh_ms_per_step": r32["refresh_ms"] / args.steps,
+        "window_hops_per_sample": r32["window_hops"],
+        "fp32_window_hops_per_s": [round(v) for v in r32["windows"]],
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_hops<float>", "bytes_per_hop": bytes_per_hop,
+                     "kernel": f"k_hops_fx<128, {1 if args.M <= 1024 else 2}>", "bytes_per_hop": bytes_per_hop,
                      "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
     }
     if r64 is not None:
         out["fp64_value"] = r64["hops"] / r64["seconds"]
+        out["fp64_window_hops_per_s"] = [round(v) for v in r64["windows"]]
         out["fp64_ms_per_step"] = r64["seconds"] / args.steps * 1e3
+    if args.large_L:
+        out["large_lattice_fp64"] = large_lattice(cg, torch, args.large_L, args.large_hops, args.large_hops // 4)
     if not args.skip_cpu:
         cores = args.cpu_cores or min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_hops, samples[0].seed, cores)
+        out["cpu_baseline"] = cpu_baseline(args.warmup * args.hops_per_step, args.cpu_hops, samples[0].seed, cores)
     print(json.dumps(out), flush=True)
     return 0
 

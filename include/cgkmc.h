@@ -42,7 +42,8 @@ extern "C" {
 #define CG_OK 0
 #define CG_EINVAL (-1)   /* invalid argument (rc >= L/2, T <= 0, bad index, ...)        */
 #define CG_ENOSPC (-2)   /* arena too small, or a sample does not fit the kernel's LDS */
-#define CG_EHIP (-3)     /* HIP runtime error; message in cg_last_error()                */
+#define CG_EHIP (-3)     /* HIP runtime error, or a workgroup of the whole-GPU kernel missed a
+                            grid barrier (bounded wait); message in cg_last_error()      */
 #define CG_ESTALL (-4)   /* label cap reached before the requested hops; state is valid */
 
 #define CG_FP64 0          /* proposals, acceptance and energy update in FP64            */
@@ -52,9 +53,11 @@ extern "C" {
 #define CG_CLOCK_GAUSS 1  /* dt ~ Gaussian(m/Gamma, sqrt(m)/Gamma), clamped at 0 (step 3c) */
 
 /* One independent sample (disorder realisation / temperature / size).
- * Requirements: 3 <= L <= 192; 1 <= n_electrons < L*L; W >= 0; xi > 0;
- * 1 <= rc < L/2 (hops longer than L/2 are excluded, section "Results ... two
- * dimensions"); T > 0. */
+ * Requirements: 3 <= L <= 192, or L a power of two in [256, 2048]; 1 <= n_electrons < L*L;
+ * W >= 0; xi > 0; 1 <= rc < L/2 (hops longer than L/2 are excluded, section "Results ...
+ * two dimensions"); T > 0.  A batch with any L > 192 runs every sample, one after the other,
+ * on the whole GPU (one cooperative launch per sample, FP64 form, every L a power of two in
+ * [128, 2048], no use_graph). */
 typedef struct cg_sample_desc {
   int32_t L;
   int32_t n_electrons;
@@ -89,7 +92,9 @@ typedef struct cg_run_opts {
                           3 = exact-geometry FP32 kernel (every sample L = 64, or every
                           sample L = 128): table by raw row difference, energies as
                           hi + lo pairs renormalised every 16 hops, precomputed
-                          acceptance thresholds                                         */
+                          acceptance thresholds;
+                          4 = whole-GPU kernel (FP64, L a power of two >= 128): each
+                          sample on every CU, automatic for L > 192                     */
   int32_t reserved;    /* set to 0                                                       */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;
@@ -112,9 +117,11 @@ typedef struct cg_stats {
   int32_t status;       /* CG_OK, or CG_ESTALL if the label cap stopped this sample     */
   int32_t since_refresh;/* hops since the last refresh (FP32 form)                      */
   int64_t logged;       /* entries written to the hop log                              */
-  uint64_t phase_cycles[4]; /* with phase_timers: shader cycles in label drawing,
-                               evaluation + lowest-label reduction, hop execution, and the
-                               energy update (each including its barrier)              */
+  uint64_t phase_cycles[4]; /* with phase_timers, shader cycles of workgroup wave 0 in:
+                               [0] label drawing, [1] evaluation up to the round barrier,
+                               [2] (exact-geometry kernel) the round barrier and hop
+                               execution, else evaluation's barrier is in [1] and [2] is
+                               hop execution, [3] the energy update and its barrier      */
 } cg_stats;
 
 typedef struct cg_ctx cg_ctx;

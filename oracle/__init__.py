@@ -57,6 +57,10 @@ def lib():
         L.or_philox.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
         L.or_create.argtypes = [P(_Params), P(C.c_void_p)]
         L.or_create.restype = C.c_int
+        L.or_create_lazy.argtypes = [P(_Params), P(C.c_void_p)]
+        L.or_create_lazy.restype = C.c_int
+        L.or_site_eps.argtypes = [C.c_void_p, C.c_int32]
+        L.or_site_eps.restype = C.c_double
         L.or_destroy.argtypes = [C.c_void_p]
         L.or_dims.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
         L.or_tower.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_int32), P(C.c_int32),
@@ -109,12 +113,14 @@ class Oracle:
     """One sample of the serial chain (FP64)."""
 
     def __init__(self, L, n_e, W=1.0, xi=1.0, rc=6.0, T=0.1, E=0.0, seed=1, sample_id=0,
-                 clock_mode=0):
+                 clock_mode=0, lazy=False):
+        """lazy=True: occupation, disorder and proposal law only (no O(N^2) energies; run()
+        is unavailable, site_eps() works) -- for lattices too large for the full recompute."""
         self.params = dict(L=L, n_e=n_e, W=W, xi=xi, rc=rc, T=T, E=E, seed=seed,
                            sample_id=sample_id, clock_mode=clock_mode)
         p = _Params(L, n_e, W, xi, rc, T, E, seed, sample_id, clock_mode)
         h = C.c_void_p()
-        rc_ = lib().or_create(C.byref(p), C.byref(h))
+        rc_ = (lib().or_create_lazy if lazy else lib().or_create)(C.byref(p), C.byref(h))
         if rc_ != 0:
             raise ValueError(f"or_create failed ({rc_}) for {self.params}")
         self._h = h
@@ -186,8 +192,14 @@ class Oracle:
         lj = np.zeros(max(cap, 1), np.int32)
         done = lib().or_run(self._h, n_hops, t_end, max_labels, _ptr(lab, C.c_uint64),
                             _ptr(li, C.c_int32), _ptr(lj, C.c_int32), cap)
+        if done < 0:
+            raise ValueError("run() needs the energies: this oracle was created lazy")
         k = min(done, cap)
         return lab[:k].copy(), li[:k].copy(), lj[:k].copy()
+
+    def site_eps(self, l: int) -> float:
+        """eps_l of the current occupation, O(N), same summation order as the full recompute."""
+        return float(lib().or_site_eps(self._h, int(l)))
 
     def recompute_eps(self) -> np.ndarray:
         a = np.zeros(self.N, np.float64)

@@ -55,6 +55,7 @@ static double unit52(uint32_t hi, uint32_t lo) {
 struct or_state {
   or_params p;
   int32_t N;
+  int32_t lazy; /* created without energies (occupation and disorder only) */
   double nu;
   /* proposal law */
   int32_t n_orb, n_vec;
@@ -218,21 +219,28 @@ double or_vec_prob(const or_state* st, int32_t v) {
 /* ------------------------------------------------------------------------- */
 /* eps_l = phi_l + sum_{m != l} (n_m - nu) / r_lm, summed over m = 0..N-1 in order
  * (definition of the single-particle energies after Eq. 2).                     */
-static void eps_from_occ(const or_state* st, double* out) {
+static double site_eps(const or_state* st, int32_t l) {
   const int32_t L = st->p.L, N = st->N;
-  for (int32_t l = 0; l < N; ++l) {
-    int32_t xl = l % L, yl = l / L;
-    double acc = st->phi[l];
-    for (int32_t m = 0; m < N; ++m) {
-      if (m == l) continue;
-      double q = (g_mutation == 7) ? (double)st->n[m] : (double)st->n[m] - st->nu;
-      acc = acc + q * or_invr(st, xl - m % L, yl - m / L);
-    }
-    out[l] = acc;
+  int32_t xl = l % L, yl = l / L;
+  double acc = st->phi[l];
+  for (int32_t m = 0; m < N; ++m) {
+    if (m == l) continue;
+    double q = (g_mutation == 7) ? (double)st->n[m] : (double)st->n[m] - st->nu;
+    acc = acc + q * or_invr(st, xl - m % L, yl - m / L);
   }
+  return acc;
+}
+
+static void eps_from_occ(const or_state* st, double* out) {
+  for (int32_t l = 0; l < st->N; ++l) out[l] = site_eps(st, l);
 }
 
 void or_recompute_eps(const or_state* st, double* out) { eps_from_occ(st, out); }
+
+double or_site_eps(const or_state* st, int32_t l) {
+  if (l < 0 || l >= st->N) return 0.0 / 0.0;
+  return site_eps(st, l);
+}
 
 /* Field-free part of Eq. 1: sum_i phi_i n_i + 1/2 sum_{i != j} (n_i-nu)(n_j-nu)/r_ij. */
 double or_energy(const or_state* st) {
@@ -263,7 +271,7 @@ static int cmp_key(const void* x, const void* y) {
   return p->i < q->i ? -1 : (p->i > q->i);
 }
 
-int or_create(const or_params* p, or_state** out) {
+static int create(const or_params* p, or_state** out, int32_t lazy) {
   *out = NULL;
   if (p->L < 3 || p->L > 4096) return -1;
   int32_t N = p->L * p->L;
@@ -276,6 +284,7 @@ int or_create(const or_params* p, or_state** out) {
   if (!st) return -2;
   st->p = *p;
   st->N = N;
+  st->lazy = lazy;
   st->nu = (double)p->n_e / (double)N;
   int rc = build_tower(st);
   st->invr = (double*)malloc(sizeof(double) * (size_t)N);
@@ -306,11 +315,19 @@ int or_create(const or_params* p, or_state** out) {
     stream(st, (uint64_t)i, TAG_PHI, w);
     st->phi[i] = p->W * (2.0 * unit52(w[0], w[1]) - 1.0);
   }
-  eps_from_occ(st, st->eps);
-  st->H0 = or_energy(st);
+  if (lazy) {
+    for (int32_t i = 0; i < N; ++i) st->eps[i] = 0.0 / 0.0;
+    st->H0 = 0.0 / 0.0;
+  } else {
+    eps_from_occ(st, st->eps);
+    st->H0 = or_energy(st);
+  }
   *out = st;
   return 0;
 }
+
+int or_create(const or_params* p, or_state** out) { return create(p, out, 0); }
+int or_create_lazy(const or_params* p, or_state** out) { return create(p, out, 1); }
 
 void or_destroy(or_state* st) {
   if (!st) return;
@@ -360,8 +377,10 @@ int or_set_occ(or_state* st, const uint8_t* n) {
   }
   if (c != st->p.n_e) return -1;
   memcpy(st->n, n, (size_t)st->N);
-  eps_from_occ(st, st->eps);
-  st->H0 = or_energy(st);
+  if (!st->lazy) {
+    eps_from_occ(st, st->eps);
+    st->H0 = or_energy(st);
+  }
   return 0;
 }
 
@@ -455,6 +474,7 @@ static void advance_clock(or_state* st, uint64_t m) {
 int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
                uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap) {
   int64_t done = 0, scanned = 0;
+  if (st->lazy) return -1; /* no energies to run with */
   for (;;) {
     if (n_hops > 0 && done >= n_hops) break;
     if (t_end >= 0.0 && st->t >= t_end) break;

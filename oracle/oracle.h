@@ -69,6 +69,13 @@ void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* Create and initialise a sample (random occupation, disorder, energies).
  * Returns 0 on success, -1 on invalid parameters, -2 on allocation failure. */
 int or_create(const or_params* p, or_state** out);
+/* The same without the O(N^2) energies and energy total (for lattices too large for
+ * them): occupation, disorder and proposal law only.  or_run refuses such a state;
+ * or_site_eps works on it. */
+int or_create_lazy(const or_params* p, or_state** out);
+/* eps_l of the current occupation in O(N): phi_l + sum_{m != l} (n_m - nu) / r_lm with m
+ * summed in index order, the same arithmetic as the full recompute. */
+double or_site_eps(const or_state* st, int32_t l);
 void or_destroy(or_state* st);
 
 /* Sizes of the proposal law. */
@@ -89,11 +96,12 @@ void or_get_phi(const or_state* st, double* out);
 void or_get_eps(const or_state* st, double* out);
 void or_get_scalars(const or_state* st, or_scalars* out);
 
-/* Replace the occupation (exactly n_e ones) and recompute eps and H0 from it.
+/* Replace the occupation (exactly n_e ones) and recompute eps and H0 from it (a lazy state
+ * only takes the occupation).
  * Clock, dipole and labels are left unchanged.  Returns 0 or -1. */
 int or_set_occ(or_state* st, const uint8_t* n);
 
-/* Run the serial chain until n_hops more hops have executed, or (t_end >= 0)
+/* Run the serial chain (not on a lazy state: returns -1) until n_hops more hops have executed, or (t_end >= 0)
  * until the first hop that brings the clock to t >= t_end, or until max_labels
  * more labels were examined (max_labels <= 0: no cap).  Executed hops are
  * logged (label, i, j) while log_cap allows; logs may be NULL.

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "cgkmc.h"
+#include "hop_big.hpp"
 #include "hop_fx.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
@@ -58,6 +59,7 @@ struct HostTables {
   std::vector<uint8_t> guide;
   std::vector<uint16_t> guide16;  // kRaw: orbit | 0x8000 when a threshold lies inside the bucket
   std::vector<int32_t> vec8;      // kRaw: [n_orb][8][2] member (dx, dy) packed, FP32 1/|d| bits
+  std::vector<double> tdo64;      // kBig: FP64 1/|d| per orbit
   std::vector<double> tab64;  // full folded table
   std::vector<double> tabk64;
   std::vector<float> tabk32;
@@ -126,7 +128,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
     while (o < n_orb - 1 && w >= (uint64_t)t.thr[o]) ++o;
     t.guide[k] = (uint8_t)o;
   }
-  if (layout == kRaw) {
+  if (layout == kRaw || layout == kBig) {
     // 16-bit guide: a bucket [w, w + 2^22) needs the threshold search only if some
     // threshold of an orbit before the last lies strictly inside it
     t.guide16.assign(kGuideSize, 0);
@@ -150,6 +152,8 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
         t.vec8[(size_t)(o * 8 + m) * 2 + 1] = bits;
       }
     }
+    t.tdo64.resize(n_orb);
+    for (int32_t o = 0; o < n_orb; ++o) t.tdo64[o] = 1.0 / std::sqrt((double)reps[o].r2);
   }
   // 1/r by folded separation (|dy|, |dx|), minimum image, 1/r(0) := 0
   const int32_t H = L / 2, H1 = H + 1;
@@ -161,7 +165,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
       t.tab64[(size_t)ay * H1 + ax] = r2 == 0 ? 0.0 : 1.0 / std::sqrt((double)r2);
     }
   const size_t nk = layout == kTri ? (size_t)tri_entries(H)
-                    : layout == kRaw ? (size_t)fx_tab_entries(L) : (size_t)full_entries(H);
+                    : layout == kRaw ? (size_t)fx_tab_entries(L) : layout == kBig ? 0 : (size_t)full_entries(H);
   std::vector<double> k64(nk, 0.0);
   if (layout == kRaw) {
     // row b = dy + L, column u = folded |dx| (zero beyond L/2)
@@ -170,7 +174,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
       const int32_t a = std::abs(b - L), ay = std::min(a, L - a);
       for (int32_t u = 0; u < H1; ++u) k64[(size_t)b * Pp + u] = t.tab64[(size_t)ay * H1 + u];
     }
-  } else {
+  } else if (layout != kBig) {
     for (int32_t ay = 0; ay < H1; ++ay)
       for (int32_t ax = 0; ax < H1; ++ax) {
         size_t idx;
@@ -189,6 +193,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
     t.tabk32.resize(nk);
     for (size_t k = 0; k < nk; ++k) t.tabk32[k] = (float)k64[k];
   }
+  if (layout == kBig) return CG_OK;  // FP64 form only: no transform-based refresh
   // refresh tables: twiddles (cos, sin)(2 pi j / L) and the x-transform of 1/r,
   // That(k, dy) = sum_dx T(fold dx, fold dy) cos(2 pi k dx / L) -- real because T is even in dx
   const double two_pi = 6.283185307179586;
@@ -231,8 +236,8 @@ int32_t count_vectors(double rc) {
 
 // ---------------------------------------------------------------------------------
 struct SampleLayout {
-  size_t tab64, tabk, thr, orb, vec, guide, vec8, guide16, dft_tw, dft_T, static_end;  // uploaded in one copy
-  size_t eps, phi, occ, part, log_label, log_from, log_to, end;
+  size_t tab64, tabk, thr, orb, vec, guide, vec8, guide16, tdo64, dft_tw, dft_T, static_end;  // uploaded in one copy
+  size_t eps, phi, occ, part, log_label, log_from, log_to, mirror, sel, end;
   int32_t dft, dft_kc, dft_rows;
 };
 
@@ -240,6 +245,7 @@ struct Plan {
   int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0, timers = 0;
   int32_t use_graph = 0, variant = 0;
   bool use_db = false, use_fx = false;
+  bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
   uint64_t max_labels = 1ull << 32;
@@ -258,9 +264,12 @@ int max_lds_bytes(int32_t* out) {
   return CG_OK;
 }
 
+bool big_eligible(int32_t L) { return L >= 128 && L <= 2048 && (L & (L - 1)) == 0; }
+
 int validate(const cg_sample_desc& d, int32_t b) {
   const int32_t L = d.L;
-  if (L < 3 || L > 192) return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 192]", b, L);
+  if (L < 3 || (L > 192 && !big_eligible(L)))
+    return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 192] and not a power of two in [256, 2048]", b, L);
   const int32_t N = L * L;
   if (d.n_electrons < 1 || d.n_electrons >= N)
     return set_err(CG_EINVAL, "sample %d: n_electrons=%d outside [1, N-1]", b, d.n_electrons);
@@ -292,7 +301,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.timers = o->phase_timers;
   if (o->use_graph != 0 && o->use_graph != 1) return set_err(CG_EINVAL, "use_graph=%d", o->use_graph);
   p.use_graph = o->use_graph;
-  if (o->variant < 0 || o->variant > 3) return set_err(CG_EINVAL, "variant=%d", o->variant);
+  if (o->variant < 0 || o->variant > 4) return set_err(CG_EINVAL, "variant=%d", o->variant);
   p.variant = o->variant;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
@@ -314,8 +323,20 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   int32_t need_db = 0;
   int32_t max_L_all = 0;
   for (int32_t b = 0; b < n; ++b) max_L_all = std::max(max_L_all, s[b].L);
+  p.big = max_L_all > 192 || p.variant == 4;
+  if (p.big) {
+    for (int32_t b = 0; b < n; ++b) {
+      int rc = validate(s[b], b);
+      if (rc != CG_OK) return rc;
+      if (!big_eligible(s[b].L))
+        return set_err(CG_EINVAL, "sample %d: L=%d; the whole-GPU kernel (L > 192 or variant 4) needs every L a "
+                       "power of two in [128, 2048]", b, s[b].L);
+    }
+    if (p.precision != CG_FP64) return set_err(CG_EINVAL, "the whole-GPU kernel (L > 192 or variant 4) runs the FP64 form");
+    if (p.use_graph) return set_err(CG_EINVAL, "use_graph is not available with the whole-GPU kernel");
+  }
   int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
-  for (int32_t b = 0; b < n; ++b) {
+  for (int32_t b = 0; b < n && !p.big; ++b) {
     int rc = validate(s[b], b);
     if (rc != CG_OK) return rc;
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
@@ -344,7 +365,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     max_orb = std::max(max_orb, count_orbits(s[b].rc));
   }
   const int32_t need_fx = fx_lds(s[0].L, max_orb).total;
-  const bool fx_ok = p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
+  const bool fx_ok = !p.big && p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
                      need_fx <= lds_cap;
   p.use_fx = fx_ok && (p.variant == 0 || p.variant == 3);
   if (p.variant == 3 && !p.use_fx)
@@ -355,7 +376,10 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (p.variant == 2 && !p.use_db)
     return set_err(CG_EINVAL, "variant 2 (one barrier per hop) needs the FP32 form, L <= 128 and %d bytes of LDS",
                    need_db);
-  if (p.use_fx) {
+  if (p.big) {
+    p.layout = kBig;
+    p.lds_hop = big_lds(max_orb).total;
+  } else if (p.use_fx) {
     p.layout = kRaw;
     p.lds_hop = need_fx;
   } else if (p.use_db) {
@@ -371,9 +395,11 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     return set_err(CG_ENOSPC, "a sample needs %d bytes of LDS for its energies and tables (%d available)",
                    p.precision == CG_FP64 ? need_tri : need_full, lds_cap);
   }
-  if (need_exact + 2 * kInitBlock * 8 > lds_cap)
+  if (!p.big && need_exact + 2 * kInitBlock * 8 > lds_cap)
     return set_err(CG_ENOSPC, "refresh kernel needs %d bytes of LDS", need_exact);
   p.lds_exact = need_exact;
+  if (p.big)
+    for (int32_t b = 0; b < n; ++b) max_N = std::max(max_N, s[b].L * s[b].L);
   p.max_N = max_N;
 
   size_t off = 0;
@@ -384,8 +410,10 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   for (int32_t b = 0; b < n; ++b) {
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
-    const int32_t ntab = p.layout == kTri ? tri_entries(H) : p.layout == kRaw ? fx_tab_entries(L) : full_entries(H);
+    const int32_t ntab = p.layout == kTri ? tri_entries(H)
+                         : p.layout == kRaw ? fx_tab_entries(L) : p.layout == kBig ? 0 : full_entries(H);
     const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
+    const bool bigl = p.layout == kBig, sel16 = p.layout == kRaw || bigl;
     max_L = std::max(max_L, L);
     SampleLayout& q = p.sl[b];
     // refresh by Fourier transform when every thread's outputs fit its registers and a
@@ -394,7 +422,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     const int32_t fixed = align16(NW * 4) + L * 16 + 512;
     int32_t kc = std::min<int32_t>(H + 1, (lds_cap - fixed) / (24 * L));
     kc = std::min<int32_t>(kc, kDftItems * 1024 / L);
-    q.dft = (G >= 1 && (L + G - 1) / G <= kDftRowsMax && kc >= 1) ? 1 : 0;
+    q.dft = (!bigl && G >= 1 && (L + G - 1) / G <= kDftRowsMax && kc >= 1) ? 1 : 0;
     q.dft_rows = G >= 1 ? (L + G - 1) / G : 0;
     if (q.dft) (q.dft_rows > 16 ? p.dft32 : p.dft16) = true;
     q.dft_kc = q.dft ? kc : 0;
@@ -406,10 +434,11 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.orb = off;       off = align_up(off + (size_t)n_orb * 4);
     q.vec = off;       off = align_up(off + (size_t)n_vec * 4);
     q.guide = off;     off = align_up(off + kGuideSize);
-    q.vec8 = off;      off = align_up(off + (p.layout == kRaw ? (size_t)n_orb * 64 : 0));
-    q.guide16 = off;   off = align_up(off + (p.layout == kRaw ? (size_t)kGuideSize * 2 : 0));
-    q.dft_tw = off;    off = align_up(off + (size_t)L * 16);
-    q.dft_T = off;     off = align_up(off + (size_t)(H + 1) * L * 8);
+    q.vec8 = off;      off = align_up(off + (sel16 ? (size_t)n_orb * 64 : 0));
+    q.guide16 = off;   off = align_up(off + (sel16 ? (size_t)kGuideSize * 2 : 0));
+    q.tdo64 = off;     off = align_up(off + (bigl ? (size_t)n_orb * 8 : 0));
+    q.dft_tw = off;    off = align_up(off + (bigl ? 0 : (size_t)L * 16));
+    q.dft_T = off;     off = align_up(off + (bigl ? 0 : (size_t)(H + 1) * L * 8));
     q.static_end = off;
     q.eps = off;       off = align_up(off + (size_t)N * 8);  // double, or FP32 value + low part
     q.phi = off;       off = align_up(off + (size_t)N * 8);
@@ -418,6 +447,8 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.log_label = off; off = align_up(off + (size_t)p.log_cap * 8);
     q.log_from = off;  off = align_up(off + (size_t)p.log_cap * 4);
     q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
+    q.mirror = off;    off = align_up(off + (bigl ? (size_t)N * 8 : 0));
+    q.sel = off;       off = align_up(off + (bigl ? sizeof(OccSelect) : 0));
     q.end = off;
   }
   p.NC = max_L <= 64 ? 1 : (max_L <= 128 ? 2 : 3);
@@ -456,11 +487,35 @@ HopFn pick_db(int32_t U, int32_t NC, bool exact) {
   return exact ? k_hops_db<2, 2, 8, true> : k_hops_db<2, 2, 8, false>;
 }
 
-HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db) {
-  if (layout == kRaw) {
-    if (NC == 1) return U == 1 ? k_hops_fx<64, 1> : k_hops_fx<64, 2>;
-    return U == 1 ? k_hops_fx<128, 1> : k_hops_fx<128, 2>;
+using BigFn = void (*)(const DevSample*, int32_t, RunArgs);
+
+// Whole-GPU kernel for one sample of side L: workgroups of 1024 threads owning SPT sites per
+// thread, G = L^2 / (1024 SPT) workgroups (16 at L = 128 up to 256 from L = 512).
+template <int U, int CLOCK>
+BigFn pick_big_uc(int32_t L, int32_t* grid) {
+  switch (L) {
+    case 128: *grid = 16; return k_hops_big<7, 1, U, CLOCK>;
+    case 256: *grid = 64; return k_hops_big<8, 1, U, CLOCK>;
+    case 512: *grid = 256; return k_hops_big<9, 1, U, CLOCK>;
+    case 1024: *grid = 256; return k_hops_big<10, 4, U, CLOCK>;
+    case 2048: *grid = 256; return k_hops_big<11, 16, U, CLOCK>;
+    default: *grid = 0; return nullptr;
   }
+}
+
+BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t* grid) {
+  if (clock == CG_CLOCK_GAUSS) return U == 1 ? pick_big_uc<1, 1>(L, grid) : pick_big_uc<2, 1>(L, grid);
+  return U == 1 ? pick_big_uc<1, 0>(L, grid) : pick_big_uc<2, 0>(L, grid);
+}
+
+template <int CLOCK>
+HopFn pick_fx(int32_t U, int32_t NC) {
+  if (NC == 1) return U == 1 ? k_hops_fx<64, 1, CLOCK> : k_hops_fx<64, 2, CLOCK>;
+  return U == 1 ? k_hops_fx<128, 1, CLOCK> : k_hops_fx<128, 2, CLOCK>;
+}
+
+HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock) {
+  if (layout == kRaw) return clock == CG_CLOCK_GAUSS ? pick_fx<1>(U, NC) : pick_fx<0>(U, NC);
   if (db) return pick_db(U, NC, exact);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
@@ -487,6 +542,7 @@ struct cg_ctx {
   int32_t* d_order = nullptr;
   int32_t* d_pending = nullptr;
   HopFn hop = nullptr;
+  std::vector<std::pair<BigFn, int32_t>> big;  // whole-GPU kernel and grid per sample
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_hop, ev_ref;
   double acc_hop_ms = 0.0, acc_ref_ms = 0.0;
   int64_t n_hop = 0, n_ref = 0;
@@ -573,8 +629,21 @@ int launch_hops(cg_ctx* c, int time_mode) {
   int rc = ev_begin(c, c->ev_hop, c->acc_hop_ms, &start);
   if (rc != CG_OK) return rc;
   const int32_t n = (int32_t)c->desc.size();
-  hipLaunchKernelGGL(c->hop, dim3(n), dim3(p.block), p.lds_hop, c->stream, c->d_samples, c->d_order, ra);
-  HIPCHK(hipGetLastError());
+  if (p.big) {
+    // one cooperative launch per sample, each on the whole GPU
+    for (int32_t b = 0; b < n; ++b) {
+      const DevSample* ds = c->d_samples;
+      int32_t sb = b;
+      hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, c->stream, c->d_samples, b);
+      HIPCHK(hipGetLastError());
+      void* args[] = {(void*)&ds, (void*)&sb, (void*)&ra};
+      HIPCHK(hipLaunchCooperativeKernel((const void*)c->big[b].first, dim3(c->big[b].second), dim3(1024), args,
+                                        (unsigned)p.lds_hop, c->stream));
+    }
+  } else {
+    hipLaunchKernelGGL(c->hop, dim3(n), dim3(p.block), p.lds_hop, c->stream, c->d_samples, c->d_order, ra);
+    HIPCHK(hipGetLastError());
+  }
   ++c->n_hop;
   return ev_end(c, c->ev_hop, start);
 }
@@ -599,7 +668,15 @@ int launch_exact(cg_ctx* c, int refresh) {
       HIPCHK(hipGetLastError());
     }
   }
-  if (!refresh || p.any_exact_refresh || p.precision == CG_FP64) {
+  if (p.big) {
+    for (int32_t b = 0; b < n; ++b) {
+      const int32_t nb = (c->desc[b].L * c->desc[b].L + kInitBlock - 1) / kInitBlock;
+      hipLaunchKernelGGL(k_eps_big, dim3(nb), dim3(kInitBlock), 0, c->stream, c->d_samples + b, refresh);
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(64), 0, c->stream, c->d_samples, refresh, p.K);
+    HIPCHK(hipGetLastError());
+  } else if (!refresh || p.any_exact_refresh || p.precision == CG_FP64) {
     if (p.precision == CG_FP64)
       hipLaunchKernelGGL(k_eps_exact<double>, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples,
                          refresh, p.K);
@@ -628,6 +705,9 @@ int check_stall(cg_ctx* c) {
   std::vector<SampleState> st;
   int rc = read_states(c, st);
   if (rc != CG_OK) return rc;
+  for (size_t b = 0; b < st.size(); ++b)
+    if (st[b].status == -3)
+      return set_err(CG_EHIP, "sample %zu: a workgroup of the whole-GPU kernel missed a grid barrier", b);
   for (size_t b = 0; b < st.size(); ++b)
     if (st[b].status != 0)
       return set_err(CG_ESTALL, "sample %zu reached the label cap (%llu labels) before its target", b,
@@ -677,7 +757,30 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   c->d_samples = (DevSample*)(c->arena + p.samples_off);
   c->d_order = (int32_t*)(c->arena + p.order_off);
   c->d_pending = (int32_t*)(c->arena + p.scratch_off);
-  c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db);
+  if (p.big) {
+    int ncu = 0, dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    c->big.resize(n);
+    for (int32_t b = 0; b < n && e == hipSuccess; ++b) {
+      int32_t g = 0;
+      BigFn fn = pick_big(samples[b].L, p.U, p.clock, &g);
+      int per_cu = 0;
+      if (fn) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 1024, p.lds_hop);
+      if (e == hipSuccess && (!fn || (int64_t)per_cu * ncu < g)) {
+        delete c;
+        return set_err(CG_ENOSPC, "sample %d: the whole-GPU kernel needs %d co-resident workgroups (%d x %d available)",
+                       b, g, per_cu, ncu);
+      }
+      c->big[b] = {fn, g};
+    }
+    if (e != hipSuccess) {
+      delete c;
+      return set_err(CG_EHIP, "whole-GPU kernel set-up: %s", hipGetErrorString(e));
+    }
+  } else {
+    c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock);
+  }
 
   auto fail = [&](int code) {
     delete c;
@@ -709,10 +812,11 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     std::memcpy(base + q.orb, t.orb.data(), t.orb.size() * 4);
     std::memcpy(base + q.vec, t.vec.data(), t.vec.size() * 4);
     std::memcpy(base + q.guide, t.guide.data(), t.guide.size());
-    if (p.layout == kRaw) {
+    if (p.layout == kRaw || p.layout == kBig) {
       std::memcpy(base + q.vec8, t.vec8.data(), t.vec8.size() * 4);
       std::memcpy(base + q.guide16, t.guide16.data(), t.guide16.size() * 2);
     }
+    if (p.layout == kBig) std::memcpy(base + q.tdo64, t.tdo64.data(), t.tdo64.size() * 8);
     std::memcpy(base + q.dft_tw, t.dft_tw.data(), t.dft_tw.size() * 8);
     std::memcpy(base + q.dft_T, t.dft_T.data(), t.dft_T.size() * 8);
 
@@ -758,6 +862,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.guide = a + q.guide;
     s.vec8 = (const int32_t*)(a + q.vec8);
     s.guide16 = (const uint16_t*)(a + q.guide16);
+    s.tdo64 = (const double*)(a + q.tdo64);
+    s.mirror = (double*)(a + q.mirror);
     s.part = (double*)(a + q.part);
     s.dft_tw = (const double*)(a + q.dft_tw);
     s.dft_T = (const double*)(a + q.dft_T);
@@ -785,7 +891,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   HIPCHK_C(hipMemcpyAsync(c->d_samples, c->dev.data(), sizeof(DevSample) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK_C(hipMemcpyAsync(c->d_order, p.order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
 
-  HIPCHK_C(hipFuncSetAttribute((const void*)c->hop, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop));
+  if (!p.big)
+    HIPCHK_C(hipFuncSetAttribute((const void*)c->hop, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop));
   if (p.precision == CG_FP64) {
     HIPCHK_C(hipFuncSetAttribute((const void*)k_eps_exact<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  p.lds_exact));
@@ -804,13 +911,36 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   const dim3 grid((p.max_N + kInitBlock - 1) / kInitBlock, n);
   hipLaunchKernelGGL(k_init_keys, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
   HIPCHK_C(hipGetLastError());
-  hipLaunchKernelGGL(k_init_rank, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
-  HIPCHK_C(hipGetLastError());
+  if (p.big) {
+    // exact selection of the n_e smallest keys, one sample at a time
+    for (int32_t b = 0; b < n; ++b) {
+      const DevSample* ds = c->d_samples + b;
+      OccSelect* sel = (OccSelect*)(c->arena + p.sl[b].sel);
+      const int32_t nb = (samples[b].L * samples[b].L + kInitBlock - 1) / kInitBlock;
+      hipLaunchKernelGGL(k_occ_clear, dim3(65536 / kInitBlock), dim3(kInitBlock), 0, c->stream, sel);
+      hipLaunchKernelGGL(k_occ_hist, dim3(nb), dim3(kInitBlock), 0, c->stream, ds, sel);
+      hipLaunchKernelGGL(k_occ_select, dim3(1), dim3(1024), 0, c->stream, ds, sel);
+      hipLaunchKernelGGL(k_occ_collect, dim3(nb), dim3(kInitBlock), 0, c->stream, ds, sel);
+      hipLaunchKernelGGL(k_occ_threshold, dim3(1), dim3(1024), 0, c->stream, ds, sel);
+      hipLaunchKernelGGL(k_occ_mark, dim3(nb), dim3(kInitBlock), 0, c->stream, ds, sel);
+      HIPCHK_C(hipGetLastError());
+    }
+  } else {
+    hipLaunchKernelGGL(k_init_rank, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
+    HIPCHK_C(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_init_phi, grid, dim3(kInitBlock), 0, c->stream, c->d_samples);
   HIPCHK_C(hipGetLastError());
   rc = launch_exact(c, 0);
   if (rc != CG_OK) return fail(rc);
   HIPCHK_C(hipStreamSynchronize(c->stream));
+  if (p.big) {
+    for (int32_t b = 0; b < n; ++b) {
+      uint32_t ovf = 0;
+      HIPCHK_C(hipMemcpy(&ovf, c->arena + p.sl[b].sel + offsetof(OccSelect, overflow), 4, hipMemcpyDeviceToHost));
+      if (ovf) return fail(set_err(CG_EHIP, "sample %d: initial-occupation selection overflow", b));
+    }
+  }
 #undef HIPCHK_C
   *out = c;
   return CG_OK;

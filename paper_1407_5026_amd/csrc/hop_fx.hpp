@@ -33,8 +33,8 @@ struct FxLabel {
 };
 
 struct FxShared {
-  uint32_t mask[3];  // per-round bitmask of waves holding an accepted label (triple-buffered)
   uint32_t theta;
+  uint32_t pad_;
   double t;          // Gaussian clock
 };
 
@@ -45,7 +45,14 @@ struct FxGeo {
   static constexpr int NC = L / 64;
   static constexpr int RPW = L / 16;
   static constexpr int P = fx_pitch(L);
+  static constexpr int SPL = RPW * NC;  // sites per lane
   static_assert(L == 64 || L == 128, "exact geometry: L = 64 or 128");
+  // LDS slot of site (x, y)'s energy value: the owner lane's SPL values are contiguous
+  // (owner thread (y & 15) * 64 + (x & 63), slot (y >> 4) NC + (x >> 6)), so a lane stores
+  // its values with 16-byte stores
+  __device__ static int ev_slot(int x, int y) {
+    return (((y & 15) << 6) | (x & 63)) * SPL + (y >> 4) * NC + (x >> 6);
+  }
 };
 
 // LDS accesses by 32-bit local address.  The dynamic LDS base is added once where an
@@ -53,6 +60,7 @@ struct FxGeo {
 // constant offset lands in the instruction's offset field.
 template <typename T>
 using lds_ptr = __attribute__((address_space(3))) T*;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t lds_addr_of(const uint8_t* p) {
   return (uint32_t)(uintptr_t)(lds_ptr<const uint8_t>)p;
@@ -85,18 +93,26 @@ __device__ __forceinline__ int fold_col(int x, int x0) {
 // 16-bit guide (searched through the thresholds only when the bucket holds one); member
 // w3 & (size - 1), read as w3 & 7 from the 8-slot table; acceptance uniform
 // (2 (w2 >> 9) + 1) 2^-24.
+// Per-sample values the hop loop keeps in scalar registers (read once per launch).
+struct FxConst {
+  uint32_t k0, k1, sid;  // Philox key and sample id
+  int32_t last;          // index of the last orbit
+  float Ef, mTln2;       // E and -T ln 2 in FP32
+};
+
 template <int L, int U>
-__device__ __forceinline__ void draw_fx(uint64_t base, int tid, const DevSample& S, uint32_t lds0,
-                                        const FxLds& lo, float Ef, float mTln2, FxLabel (&lb)[U]) {
+__device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C, uint32_t lds0,
+                                        const FxLds& lo, FxLabel (&lb)[U]) {
   using G = FxGeo<L>;
   const uint32_t guide = lds0 + lo.guide, thr = lds0 + lo.thr, vec8 = lds0 + lo.vec8;
   const uint32_t ev = lds0 + lo.ev, occ = lds0 + lo.occ;
-  const int last = S.n_orb - 1;
+  const int last = C.last;
+  const float Ef = C.Ef, mTln2 = C.mTln2;
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
-    uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = S.sample_id, c3 = kTagPropose;
-    philox10(c0, c1, c2, c3, S.seed_lo, S.seed_hi);
+    uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = C.sid, c3 = kTagPropose;
+    philox10(c0, c1, c2, c3, C.k0, C.k1);
     const int i = (int)(c0 >> (32 - 2 * G::LG));
     const uint32_t g = lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuideBits)));
     int o = (int)(g & 0x7fffu);
@@ -107,14 +123,15 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const DevSample&
     const int vx = (int)(uint32_t)v;
     const int dx = (int)(int16_t)(vx & 0xffff), dy = vx >> 16;
     const int xi = i & (L - 1), yi = i >> G::LG;
-    const int j = (((yi + dy) & (L - 1)) << G::LG) | ((xi + dx) & (L - 1));
+    const int xj = (xi + dx) & (L - 1), yj = (yi + dy) & (L - 1);
+    const int j = (yj << G::LG) | xj;
     const float td = __uint_as_float((uint32_t)(v >> 32));
     const float u = (float)(2u * (c2 >> 9) + 1u) * 0x1p-24f;
     FxLabel& b = lb[k];
     b.i = i;
     b.j = j;
-    b.ai = ev + 4 * i;
-    b.aj = ev + 4 * j;
+    b.ai = ev + 4 * G::ev_slot(xi, yi);
+    b.aj = ev + 4 * G::ev_slot(xj, yj);
     b.oi = occ + 4 * (i >> 5);
     b.oj = occ + 4 * (j >> 5);
     b.dx = dx;
@@ -123,11 +140,13 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const DevSample&
   }
 }
 
-template <int L, int U>
+// CLOCK = 0: deterministic clock t = s_last / Gamma; 1: Gaussian increments (step 3c), the
+// only per-hop call, kept out of the deterministic instance.
+template <int L, int U, int CLOCK>
 __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ samples,
                                                   const int32_t* __restrict__ order, RunArgs ra) {
   using G = FxGeo<L>;
-  constexpr int NW = 16, NC = G::NC, RPW = G::RPW, P = G::P;
+  constexpr int NW = 16, NC = G::NC, RPW = G::RPW, P = G::P, SPL = G::SPL;
   constexpr uint32_t M = 1024u * U;
   constexpr int kRenorm = 16;
   const DevSample& S = samples[order[blockIdx.x]];
@@ -176,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
         const float2 e = g[l];
         eh[r][c] = e.x;
         el[r][c] = e.y;
-        ev[l] = e.x + e.y;
+        ev[tid * SPL + r * NC + c] = e.x + e.y;
       }
     }
     const uint4* __restrict__ gt = (const uint4*)S.tabk;
@@ -187,23 +206,37 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
   for (int k = tid; k < S.n_orb; k += 1024) ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
   for (int k = tid; k < kGuideSize; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
   for (int k = tid; k < S.n_orb * 8; k += 1024) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
+  if (tid < kMaxWaves) info[tid] = make_uint4(0u, 0u, 0u, ~0u);  // no round has this tag
   if (tid == 0) {
-    sh->mask[0] = sh->mask[1] = sh->mask[2] = 0u;
     sh->theta = 0u;
     sh->t = t_start;
   }
   __syncthreads();
 
-  const uint32_t k0 = S.seed_lo, k1 = S.seed_hi, sid = S.sample_id;
-  const uint64_t s_end = uni((ra.time_mode && ra.clock_mode == 0) ? label_at_time(t_end, S.Gamma) : (uint64_t)0);
-  const float Ef = S.E32, mTln2 = S.mTln2_32;
-  // this lane's energy value of row wid + 16 r, column lane + 64 c is at ev_lane + r kRowEv + 256 c
-  const uint32_t ev_lane = opaque(lds0 + lo.ev + 4 * (uint32_t)(wid * L + lane));
-  constexpr int kRowEv = NW * L * 4, kRowTab = NW * P * 4;
+  FxConst C;
+  C.k0 = uni(S.seed_lo);
+  C.k1 = uni(S.seed_hi);
+  C.sid = uni(S.sample_id);
+  C.last = uni(S.n_orb - 1);
+  C.Ef = __uint_as_float(uni(__float_as_uint(S.E32)));
+  C.mTln2 = __uint_as_float(uni(__float_as_uint(S.mTln2_32)));
+  const double Gamma = uni(S.Gamma);
+  const int64_t log_cap = uni((int64_t)S.log_cap);
+  uint64_t* __restrict__ log_label = S.log_label;
+  int32_t* __restrict__ log_from = S.log_from;
+  int32_t* __restrict__ log_to = S.log_to;
+  const uint64_t s_end = uni((ra.time_mode && CLOCK == 0) ? label_at_time(t_end, Gamma) : (uint64_t)0);
+  // this lane's energy values (row wid + 16 r, column lane + 64 c at slot r NC + c) start at ev_lane
+  const uint32_t ev_lane = opaque(lds0 + lo.ev + 16u * SPL / 4 * (uint32_t)tid);
+  constexpr int kRowTab = NW * P * 4;
   bool cached = false;
   FxLabel lb[U];
+  // the chunk after the current one, drawn during a hop's update (the labels do not depend on
+  // the configuration): valid when next_base == base + M
+  FxLabel lbn[U];
+  uint64_t next_base = ~0ull;
   uint32_t theta_cnt = 0;
-  uint32_t slot = 0;
+  uint32_t round = 0;  // tag of the current evaluation round
   uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
   const bool timers = ra.timers != 0;
 #define CG_MARK(acc)                                          \
@@ -217,10 +250,15 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
   // one iteration per executed hop; the energies change only in its straight-line part
   for (;;) {
     // rounds until a round accepts a label (or the label cap stops the sample)
-    uint32_t mk = 0u;
+    uint32_t mk = 0u, win0 = 0u, win1 = 0u, win2 = 0u;
     for (;;) {
     if (!cached) {
-      draw_fx<L, U>(base, tid, S, lds0, lo, Ef, mTln2, lb);
+      if (next_base == base) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) lb[k] = lbn[k];
+      } else {
+        draw_fx<L, U>(base, tid, C, lds0, lo, lb);
+      }
       cached = true;
       CG_MARK(tc0)
     }
@@ -247,23 +285,32 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
         pdh = de - b.td;
       }
     }
-    // the wave's lowest accepting lane publishes its label; the round's winner is the
-    // lowest wave with an accepted label (keys grow with the thread index)
-    const uint32_t nxt = slot == 2u ? 0u : slot + 1u;
+    // the wave's lowest accepting lane publishes its label in the wave's record, tagged with
+    // the round; after the barrier lanes 0..15 read the 16 records and the round's winner is
+    // the lowest wave whose record carries this round's tag (keys grow with the thread
+    // index).  A record is rewritten only by its own wave: in a later round, which only
+    // happens before another wave reads it for this round if this round executed no hop
+    // from that wave, and then the later tag is simply not this round's.
     const unsigned long long bal = __ballot(first < U);
     if (bal != 0ull) {
-      if (lane == __ffsll(bal) - 1) {
-        info[wid] = make_uint4(pub0, pub1, __float_as_uint(pdh), 0u);
-        atomicOr(&sh->mask[slot], 1u << wid);
-      }
+      if (lane == __ffsll(bal) - 1) info[wid] = make_uint4(pub0, pub1, __float_as_uint(pdh), round);
     }
-    if (tid == 0) sh->mask[nxt] = 0u;
+    CG_MARK(tc1)
     __syncthreads();
-    mk = uni(sh->mask[slot]);
-    slot = nxt;
+    uint4 rec = make_uint4(0u, 0u, 0u, ~round);
+    if (lane < kMaxWaves) rec = info[lane];
+    const unsigned long long won = __ballot(rec.w == round);
+    mk = won != 0ull ? 1u : 0u;
+    if (won != 0ull) {
+      const int wl = __ffsll(won) - 1;
+      win0 = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, wl);
+      win1 = (uint32_t)__builtin_amdgcn_readlane((int)rec.y, wl);
+      win2 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, wl);
+    }
+    ++round;
     ++rounds;
     evaluated += M - dpos;
-    CG_MARK(tc1)
+    CG_MARK(tc2)
     if (mk != 0u) break;
     // every label of the chunk is rejected
     base += M;
@@ -277,9 +324,8 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     if (mk == 0u) break;
 
     // step 3: execute the lowest accepted label
-    const uint4 w = info[__ffs(mk) - 1];
-    const uint32_t w0 = uni(w.x), w1 = uni(w.y);
-    const float dh0 = __uint_as_float(uni(w.z));
+    const uint32_t w0 = win0, w1 = win1;
+    const float dh0 = __uint_as_float(win2);
     const int hi = (int)(w0 & 0xffffu), hj = (int)(w0 >> 16);
     const uint32_t key = w1 & 0xffffu;
     const int hdx = (int)w1 >> 16;
@@ -295,14 +341,14 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     if (tid == 0) {
       atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
       atomicOr(&occ[hj >> 5], 1u << (hj & 31));
-      if (logged < S.log_cap) {
-        S.log_label[logged] = q;
-        S.log_from[logged] = hi;
-        S.log_to[logged] = hj;
+      if (logged < log_cap) {
+        log_label[logged] = q;
+        log_from[logged] = hi;
+        log_to[logged] = hj;
       }
-      if (ra.clock_mode != 0) sh->t = sh->t + gauss_dt(hops, m, sid, k0, k1, S.Gamma);
+      if (CLOCK != 0) sh->t = sh->t + gauss_dt(hops, m, C.sid, C.k0, C.k1, Gamma);
     }
-    if (logged < S.log_cap) ++logged;
+    logged += logged < log_cap ? 1 : 0;
     CG_MARK(tc2)
 
     // step 3b on the owned sites: lo += 1/r_lj - 1/r_li, LDS value fl(hi + lo).  Row
@@ -326,13 +372,28 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
         for (int c = 0; c < NC; ++c)
           d[r][c] = lds_ld<float>(aj[c] + r * kRowTab) - lds_ld<float>(ai[c] + r * kRowTab);
       }
+      // while the table loads are in flight: draw the next chunk if it is not drawn yet
+      if (next_base != base + M) {
+        next_base = base + M;
+        draw_fx<L, U>(next_base, tid, C, lds0, lo, lbn);
+      }
+      float v[SPL];
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           el[r][c] = el[r][c] + d[r][c];
-          lds_st<float>(ev_lane + r * kRowEv + 256 * c, eh[r][c] + el[r][c]);
+          v[r * NC + c] = eh[r][c] + el[r][c];
         }
+      }
+#pragma unroll
+      for (int q = 0; q < SPL / 4; ++q) {
+        f32x4 w;
+        w.x = v[4 * q];
+        w.y = v[4 * q + 1];
+        w.z = v[4 * q + 2];
+        w.w = v[4 * q + 3];
+        lds_st<f32x4>(ev_lane + 16 * q, w);
       }
       if ((hops & (uint64_t)(kRenorm - 1)) == 0) {
         // Fast2Sum: z = fl(hi + lo) - hi is exact and hi + z = fl(hi + lo), so the pair
@@ -357,7 +418,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     }
     if (hops >= target) break;
     if (ra.time_mode) {
-      if (ra.clock_mode == 0 ? s_last >= s_end : uni(sh->t) >= t_end) break;
+      if (CLOCK == 0 ? s_last >= s_end : uni(sh->t) >= t_end) break;
     }
     if (ra.K > 0 && since >= ra.K) break;
   }
@@ -378,7 +439,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     gs->s_last = s_last;
     gs->s_scan = base + dpos;
     gs->P = P_;
-    gs->t = ra.clock_mode == 0 ? (double)s_last / S.Gamma : sh->t;
+    gs->t = CLOCK == 0 ? (double)s_last / Gamma : sh->t;
     gs->H0 = H0;
     gs->since_refresh = since;
     gs->status = status;

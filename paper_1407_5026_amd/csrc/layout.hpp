@@ -12,7 +12,10 @@
 //   vec   [n_vec] i32                    member displacement (dx & 0xffff) | dy << 16
 //   guide [1024] u8                      orbit at the start of each 2^22-wide bucket of w1
 //   dft_tw [L] double2, dft_T [(H+1) L] double   twiddles and transformed 1/r for the refresh
-//   vec8  [n_orb][8] int2, guide16 [1024] u16   proposal tables of the exact-geometry kernel
+//   vec8  [n_orb][8] int2, guide16 [1024] u16   proposal tables of the exact-geometry and
+//                                        large-sample kernels; tdo64 [n_orb] double (large)
+//   mirror [N] double                    large-sample kernel: energies read by the proposals
+//   sel   OccSelect                      large-sample initial-occupation selection scratch
 //   part  [2 * nblk] double              per-block partial sums (energy, drift)
 //   log   [cap] u64 + 2 x [cap] i32      executed-hop log (label, from, to)
 #pragma once
@@ -29,7 +32,9 @@ constexpr int kInitBlock = 256;     // threads per block of the init / refresh k
 
 // kFull: (H+1)^2 table by (|dy|, |dx|); kTri: its triangle |dx| <= |dy|; kRaw: the exact-geometry
 // FP32 kernel's table by raw row difference dy + L and folded column distance (see fx_pitch).
-enum TableLayout : int32_t { kFull = 0, kTri = 1, kRaw = 2 };
+// kBig: the large-sample kernel (one sample on the whole GPU): the FP64 (|dy|, |dx|) table in
+// global memory, no kernel table.
+enum TableLayout : int32_t { kFull = 0, kTri = 1, kRaw = 2, kBig = 3 };
 
 struct SampleState {
   uint64_t s_last;        // label of the last executed hop
@@ -52,7 +57,7 @@ struct SampleState {
   int32_t status;         // 0 ok, CG_ESTALL
   int32_t since_refresh;  // hops since last refresh
   int32_t force_refresh;  // refresh kernel: refresh regardless of since_refresh
-  int32_t pad_;
+  uint32_t grid_bar;      // whole-GPU kernel: arrivals at its grid barrier in this launch
   uint64_t phase_cycles[4];  // shader cycles: refill, evaluate, execute, update (if timed)
 };
 
@@ -76,6 +81,8 @@ struct DevSample {
   const uint8_t* guide;
   const int32_t* vec8;    // kRaw: [n_orb][8] (dx & 0xffff | dy << 16, bits of FP32 1/|d|)
   const uint16_t* guide16;  // kRaw: orbit at each bucket start | 0x8000 if a threshold lies inside
+  const double* tdo64;    // large-sample kernel: FP64 1/|d| per orbit
+  double* mirror;         // large-sample kernel: global copy of the energies for the proposals
   double* part;
   const double* dft_tw;   // [L] (cos, sin)(2 pi j / L)
   const double* dft_T;    // [(H+1) x L] sum_dx T(dx, dy) cos(2 pi k dx / L), row k

@@ -31,6 +31,13 @@ def oracle_of(s, clock_mode=0):
                          seed=d["seed"], sample_id=d["sample_id"], clock_mode=clock_mode)
 
 
+def lazy_oracle_of(s):
+    """Oracle with occupation, disorder and proposal law only (no O(N^2) energies)."""
+    d = s if isinstance(s, dict) else s.as_dict()
+    return oracle.Oracle(L=d["L"], n_e=d["n_e"], W=d["W"], xi=d["xi"], rc=d["rc"], T=d["T"], E=d["E"],
+                         seed=d["seed"], sample_id=d["sample_id"], lazy=True)
+
+
 def compare_logs(sample, gpu_log, or_log, tol=1e-12):
     """Hop-for-hop equality of (label, from, to).  The only allowed divergence is a flip at the
     first differing label s where the oracle's |u - P_acc| < tol; returns the number of hops that

@@ -1,0 +1,75 @@
+"""GPU parity of the whole-GPU kernel: one sample on every workgroup of a cooperative launch
+(FP64 form; L = 128 ... 2048), through the C ABI, against the serial FP64 oracle."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import compare_logs, lazy_oracle_of, oracle_of, require_gpu, say
+from workloads import Sample
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(cg, samples, **opts):
+    return cg.Batch(samples, cg.make_opts(**opts))
+
+
+@pytest.mark.parametrize("M", [1024, 2048])
+def test_whole_gpu_kernel_hop_for_hop_l128(M):
+    """Forced onto 16 workgroups at L=128 (variant 4), the kernel executes the oracle's hops,
+    labels and sites, hop for hop, and ends with its FP64 energies, dipole, clock and energy."""
+    cg = require_gpu()
+    s = Sample(128, 8192, 1.0, 1.0, 10.0, 0.05, 0.01, 41, 0)
+    hops = 2500
+    say(f"whole-GPU kernel L=128 M={M}: {hops} hops")
+    b = _batch(cg, [s], precision=cg.CG_FP64, M=M, variant=4, log_hops=hops)
+    b.run_hops(hops)
+    o = oracle_of(s)
+    agree = compare_logs(s, b.hop_log(0), o.run(hops))
+    assert agree == hops
+    assert float(np.abs(b.energies(0) - o.eps()).max()) <= 1e-12
+    st, sc = b.stats(0), o.scalars()
+    assert st["P"] == sc["P"] and st["hops"] == hops
+    assert abs(st["t"] - sc["t"]) <= 1e-12 * sc["t"]
+    assert abs(st["H0"] - sc["H0"]) <= 1e-9 * abs(sc["H0"])
+
+
+def _signed_dx(a, c, L):
+    d = (c % L) - (a % L)
+    d = np.where(d > L // 2, d - L, d)
+    return np.where(d < -(L // 2), d + L, d)
+
+
+@pytest.mark.parametrize("L,hops", [(256, 400), (1024, 200), (2048, 60)])
+def test_whole_gpu_kernel_large_lattice(L, hops):
+    """Large lattices (beyond the full oracle): the initial occupation and disorder equal the
+    oracle's, sampled initial energies equal its O(N) single-site sum bit for bit (same order);
+    after hops every logged hop moves an electron to an empty site, the occupation replays,
+    the dipole is the sum of the logged dx, and sampled energies (random sites and the sites of
+    the last hops) agree with the single-site recompute to 1e-10."""
+    cg = require_gpu()
+    s = Sample(L, L * L // 2, 1.0, 1.0, 10.0, 0.05, 0.01, 43, 1)
+    say(f"whole-GPU kernel L={L}: init")
+    b = _batch(cg, [s], precision=cg.CG_FP64, log_hops=hops)
+    lazy = lazy_oracle_of(s)
+    n0 = b.occupation(0)
+    assert np.array_equal(n0, lazy.occ())
+    assert np.array_equal(b.phi(0), lazy.phi())
+    sites = np.random.default_rng(7).choice(L * L, 16, replace=False)
+    e0 = b.energies(0)
+    for l in sites.tolist():
+        assert e0[l] == lazy.site_eps(l), l
+    say(f"whole-GPU kernel L={L}: {hops} hops")
+    b.run_hops(hops)
+    lab, fr, to = b.hop_log(0)
+    assert len(lab) == hops and np.all(np.diff(lab.astype(np.int64)) > 0)
+    n = n0.copy()
+    for a, c in zip(fr.tolist(), to.tolist()):
+        assert n[a] == 1 and n[c] == 0
+        n[a], n[c] = 0, 1
+    assert np.array_equal(n, b.occupation(0))
+    st = b.stats(0)
+    assert st["hops"] == hops and st["P"] == int(_signed_dx(fr, to, L).sum())
+    lazy.set_occ(n)
+    e = b.energies(0)
+    for l in np.concatenate([sites, fr[-4:], to[-4:]]).tolist():
+        assert abs(e[l] - lazy.site_eps(l)) <= 1e-10, l

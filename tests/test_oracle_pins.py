@@ -148,3 +148,26 @@ def test_philox_matches_torch_engine(tmp_path):
         want = np.array([int(w) for w in out], dtype=np.uint32)
         got = oracle.philox(c.astype(np.uint32), k.astype(np.uint32))
         assert np.array_equal(got, want), (c, k, got, want)
+
+
+def test_lazy_oracle_and_site_energy():
+    """The lazy oracle (no O(N^2) energies) draws the same occupation and disorder as the full
+    one, and its O(N) single-site energy equals the full recompute at every site, before and
+    after hops, bit for bit (same summation order); running a lazy state is refused."""
+    import numpy as np
+
+    import oracle
+
+    kw = dict(L=16, n_e=128, W=1.0, xi=1.0, rc=6.0, T=0.1, E=0.01, seed=11, sample_id=3)
+    full = oracle.Oracle(**kw)
+    lazy = oracle.Oracle(lazy=True, **kw)
+    assert np.array_equal(full.occ(), lazy.occ())
+    assert np.array_equal(full.phi(), lazy.phi())
+    e = full.eps()
+    assert all(lazy.site_eps(l) == e[l] for l in range(full.N))
+    full.run(300)
+    lazy.set_occ(full.occ())
+    e = full.recompute_eps()
+    assert all(lazy.site_eps(l) == e[l] for l in range(full.N))
+    with pytest.raises(ValueError):
+        lazy.run(1)
