@@ -47,11 +47,13 @@ struct FxGeo {
   static constexpr int P = fx_pitch(L);
   static constexpr int SPL = RPW * NC;  // sites per lane
   static_assert(L == 64 || L == 128, "exact geometry: L = 64 or 128");
-  // LDS slot of site (x, y)'s energy value: the owner lane's SPL values are contiguous
-  // (owner thread (y & 15) * 64 + (x & 63), slot (y >> 4) NC + (x >> 6)), so a lane stores
-  // its values with 16-byte stores
+  // LDS word of site (x, y)'s energy value.  The owner is wave y & 15, lane x & 63, slot
+  // s = (y >> 4) NC + (x >> 6); each wave's 64 SPL words are laid out as [s / 4][lane][s % 4],
+  // so the wave stores its values with SPL / 4 16-byte stores, each covering 1024
+  // contiguous bytes (lane-consecutive: no bank conflicts)
   __device__ static int ev_slot(int x, int y) {
-    return (((y & 15) << 6) | (x & 63)) * SPL + (y >> 4) * NC + (x >> 6);
+    const int s = (y >> 4) * NC + (x >> 6);
+    return (y & 15) * 64 * SPL + (s >> 2) * 256 + (x & 63) * 4 + (s & 3);
   }
 };
 
@@ -195,7 +197,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
         const float2 e = g[l];
         eh[r][c] = e.x;
         el[r][c] = e.y;
-        ev[tid * SPL + r * NC + c] = e.x + e.y;
+        ev[wid * 64 * SPL + ((r * NC + c) >> 2) * 256 + lane * 4 + ((r * NC + c) & 3)] = e.x + e.y;
       }
     }
     const uint4* __restrict__ gt = (const uint4*)S.tabk;
@@ -226,8 +228,9 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
   int32_t* __restrict__ log_from = S.log_from;
   int32_t* __restrict__ log_to = S.log_to;
   const uint64_t s_end = uni((ra.time_mode && CLOCK == 0) ? label_at_time(t_end, Gamma) : (uint64_t)0);
-  // this lane's energy values (row wid + 16 r, column lane + 64 c at slot r NC + c) start at ev_lane
-  const uint32_t ev_lane = opaque(lds0 + lo.ev + 16u * SPL / 4 * (uint32_t)tid);
+  // this lane's energy values (row wid + 16 r, column lane + 64 c at slot s = r NC + c): chunk
+  // s / 4 at ev_lane + 1024 (s / 4)
+  const uint32_t ev_lane = opaque(lds0 + lo.ev + 4u * (uint32_t)(wid * 64 * SPL + lane * 4));
   constexpr int kRowTab = NW * P * 4;
   bool cached = false;
   FxLabel lb[U];
@@ -393,7 +396,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
         w.y = v[4 * q + 1];
         w.z = v[4 * q + 2];
         w.w = v[4 * q + 3];
-        lds_st<f32x4>(ev_lane + 16 * q, w);
+        lds_st<f32x4>(ev_lane + 1024 * q, w);
       }
       if ((hops & (uint64_t)(kRenorm - 1)) == 0) {
         // Fast2Sum: z = fl(hi + lo) - hi is exact and hi + z = fl(hi + lo), so the pair
