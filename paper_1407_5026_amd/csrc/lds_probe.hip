@@ -51,6 +51,34 @@ __global__ void __launch_bounds__(1024) k_read(uint32_t* out, int iters) {
   if (acc == 0x12345678u) out[blockIdx.x * 1024 + threadIdx.x] = acc;
 }
 
+// Random-address 4-byte reads (the proposals' energy and occupation reads): each lane's next
+// address comes from a multiplicative hash of the value just read, so every read is random
+// and depends on the previous one (four independent chains per lane).
+__global__ void __launch_bounds__(1024) k_read_random(uint32_t* out, int iters) {
+  __shared__ __align__(16) uint32_t buf[kWords];
+  for (int k = threadIdx.x; k < kWords; k += 1024) buf[k] = (uint32_t)k * 2654435761u;
+  __syncthreads();
+  uint32_t a0 = threadIdx.x * 7u, a1 = threadIdx.x * 13u + 1u, a2 = threadIdx.x * 29u + 2u, a3 = threadIdx.x * 31u + 3u;
+  for (int it = 0; it < iters; ++it) {
+    a0 = (buf[a0 & (kWords - 1)] ^ a0) * 2246822519u;  // index always masked into the array
+    a1 = (buf[a1 & (kWords - 1)] ^ a1) * 2246822519u;
+    a2 = (buf[a2 & (kWords - 1)] ^ a2) * 2246822519u;
+    a3 = (buf[a3 & (kWords - 1)] ^ a3) * 2246822519u;
+    a0 >>= 3; a1 >>= 3; a2 >>= 3; a3 >>= 3;
+  }
+  if ((a0 ^ a1 ^ a2 ^ a3) == 0x12345678u) out[blockIdx.x * 1024 + threadIdx.x] = 1;
+}
+
+// Workgroup barriers only (the cost of one round trip through s_barrier with 16 waves).
+__global__ void __launch_bounds__(1024) k_barrier(uint32_t* out, int iters) {
+  uint32_t v = threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+    v = v * 1664525u + 1013904223u;
+    __syncthreads();
+  }
+  if (v == 0x12345678u) out[blockIdx.x * 1024 + threadIdx.x] = 1;
+}
+
 __global__ void __launch_bounds__(1024) k_write(uint32_t* out, int iters) {
   __shared__ __align__(16) uint32_t buf[kWords];
   uint32_t v = threadIdx.x;
@@ -191,6 +219,11 @@ int main() {
   std::printf("ds_read_b64   %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 8));
   if (timed([&] { hipLaunchKernelGGL(k_read<4>, g, b, 0, 0, out, iters); })) return 1;
   std::printf("ds_read_b128  %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 16));
+  if (timed([&] { hipLaunchKernelGGL(k_read_random, g, b, 0, 0, out, iters); })) return 1;
+  std::printf("ds_read_b32 random addresses  %8.3f ms  %7.2f clk per wave instruction per CU\n", ms,
+              ms * 1e-3 * clk / ((double)iters * 4 * 16));
+  if (timed([&] { hipLaunchKernelGGL(k_barrier, g, b, 0, 0, out, iters); })) return 1;
+  std::printf("s_barrier, 16 waves           %8.3f ms  %7.1f clk per barrier\n", ms, ms * 1e-3 * clk / iters);
   if (timed([&] { hipLaunchKernelGGL(k_write, g, b, 0, 0, out, iters); })) return 1;
   std::printf("ds_write_b32  %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 4));
   const int upd_iters = iters / 8;
