@@ -14,6 +14,11 @@
 //    the pair is renormalised exactly (Fast2Sum) so that lo stays of the order of the recent
 //    increments: its rounding errors stay far below those of a single FP32 running sum, at
 //    three vector operations per site and hop.
+//  * A site's occupation travels in the lowest bit of its energy value word: hi's lowest
+//    mantissa bit is kept equal to n_l (the change is moved into lo, so hi + lo keeps its
+//    value) and the value word fl(hi + lo) carries hi's lowest bit.  A proposal reads two
+//    words, not four (random LDS reads cost ~16 cycles per wave instruction); the value it
+//    compares is within one ulp of fl(hi + lo).
 //  * Every label carries its LDS addresses and its acceptance threshold
 //    th = 1/r_ij + E dx - T ln u, so the test of Eq. 2, dH <= 0 or u < exp(-dH/T) with
 //    dH = eps_j - eps_i - 1/r_ij - E dx, is the single comparison eps_j - eps_i <= th
@@ -24,13 +29,26 @@
 
 namespace cg {
 
-// One cached label: sites, LDS byte addresses of their energies and occupation words,
-// displacement dx, acceptance threshold and 1/r_ij.
+// One cached label: sites, LDS byte addresses of their energy value words, displacement dx,
+// acceptance threshold and 1/r_ij.
 struct FxLabel {
   int32_t i, j, dx;
-  uint32_t ai, aj, oi, oj;
+  uint32_t ai, aj;
   float th, td;
 };
+
+// Sets hi's lowest mantissa bit to the occupation n and moves the change (one ulp of hi, or
+// zero) into lo: hi + lo keeps its value up to the rounding of that addition (2^-24 ulp).
+__device__ __forceinline__ void set_mark(float& hi, float& lo, uint32_t n) {
+  const float h2 = __uint_as_float((__float_as_uint(hi) & ~1u) | n);
+  lo = lo + (hi - h2);
+  hi = h2;
+}
+
+// The value word the proposals read: fl(hi + lo) with hi's lowest bit (the occupation).
+__device__ __forceinline__ float marked(float hi, float lo) {
+  return __uint_as_float((__float_as_uint(hi + lo) & ~1u) | (__float_as_uint(hi) & 1u));
+}
 
 struct FxShared {
   uint32_t theta;
@@ -107,7 +125,7 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C
                                         const FxLds& lo, FxLabel (&lb)[U]) {
   using G = FxGeo<L>;
   const uint32_t guide = lds0 + lo.guide, thr = lds0 + lo.thr, vec8 = lds0 + lo.vec8;
-  const uint32_t ev = lds0 + lo.ev, occ = lds0 + lo.occ;
+  const uint32_t ev = lds0 + lo.ev;
   const int last = C.last;
   const float Ef = C.Ef, mTln2 = C.mTln2;
 #pragma unroll
@@ -134,8 +152,6 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C
     b.j = j;
     b.ai = ev + 4 * G::ev_slot(xi, yi);
     b.aj = ev + 4 * G::ev_slot(xj, yj);
-    b.oi = occ + 4 * (i >> 5);
-    b.oj = occ + 4 * (j >> 5);
     b.dx = dx;
     b.td = td;
     b.th = (td + Ef * (float)dx) + mTln2 * __log2f(u);
@@ -197,7 +213,8 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
         const float2 e = g[l];
         eh[r][c] = e.x;
         el[r][c] = e.y;
-        ev[wid * 64 * SPL + ((r * NC + c) >> 2) * 256 + lane * 4 + ((r * NC + c) & 3)] = e.x + e.y;
+        set_mark(eh[r][c], el[r][c], (S.occ[l >> 5] >> (l & 31)) & 1u);
+        ev[wid * 64 * SPL + ((r * NC + c) >> 2) * 256 + lane * 4 + ((r * NC + c) & 3)] = marked(eh[r][c], el[r][c]);
       }
     }
     const uint4* __restrict__ gt = (const uint4*)S.tabk;
@@ -275,10 +292,14 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     for (int k = 0; k < U; ++k) {
       const FxLabel& b = lb[k];
       const uint32_t key = (uint32_t)(tid * U + k);
-      const uint32_t wi = lds_ld<uint32_t>(b.oi), wj = lds_ld<uint32_t>(b.oj);
-      const float ei = lds_ld<float>(b.ai), ej = lds_ld<float>(b.aj);
-      const float de = ej - ei;
-      const bool th = (first == U) & (key >= dpos) & ((((wi >> (b.i & 31)) & ~(wj >> (b.j & 31))) & 1u) != 0u);
+      const bool open = (first == U) & (key >= dpos);  // not yet decided
+      uint32_t wi = 0u, wj = 0u;
+      if (open) {
+        wi = lds_ld<uint32_t>(b.ai);
+        wj = lds_ld<uint32_t>(b.aj);
+      }
+      const float de = __uint_as_float(wj) - __uint_as_float(wi);
+      const bool th = open & ((wi & ~wj & 1u) != 0u);  // n_i (1 - n_j) from the value words
       const bool acc = th & (de <= b.th);
       theta_cnt += th ? 1u : 0u;
       if (acc) {
@@ -352,6 +373,35 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
       if (CLOCK != 0) sh->t = sh->t + gauss_dt(hops, m, C.sid, C.k0, C.k1, Gamma);
     }
     logged += logged < log_cap ? 1 : 0;
+    // the owners of i and j move their occupation marks: site (x, y) is slot (y >> 4) NC +
+    // (x >> 6) of lane x & 63 in wave y & 15; the slot index is wave-uniform, so a short
+    // branch tree picks the register
+    {
+      const int xi = hi & (L - 1), yi = hi >> G::LG, xj = hj & (L - 1), yj = hj >> G::LG;
+      static_assert(SPL <= 16, "slot switch covers 16 slots");
+#define CG_SLOT(k)                                                                   \
+  case k:                                                                            \
+    if constexpr (k < SPL) {                                                         \
+      set_mark(eh[k / NC][k % NC], el[k / NC][k % NC], n);                           \
+    }                                                                                \
+    break;
+#define CG_SLOTS(sl)                                                                 \
+  switch (sl) {                                                                      \
+    CG_SLOT(0) CG_SLOT(1) CG_SLOT(2) CG_SLOT(3) CG_SLOT(4) CG_SLOT(5) CG_SLOT(6)     \
+    CG_SLOT(7) CG_SLOT(8) CG_SLOT(9) CG_SLOT(10) CG_SLOT(11) CG_SLOT(12) CG_SLOT(13) \
+    CG_SLOT(14) CG_SLOT(15) default: break;                                          \
+  }
+      if (wid == (yi & 15) && lane == (xi & 63)) {
+        const uint32_t n = 0u;
+        CG_SLOTS((yi >> 4) * NC + (xi >> 6))
+      }
+      if (wid == (yj & 15) && lane == (xj & 63)) {
+        const uint32_t n = 1u;
+        CG_SLOTS((yj >> 4) * NC + (xj >> 6))
+      }
+#undef CG_SLOTS
+#undef CG_SLOT
+    }
     CG_MARK(tc2)
 
     // step 3b on the owned sites: lo += 1/r_lj - 1/r_li, LDS value fl(hi + lo).  Row
@@ -386,7 +436,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           el[r][c] = el[r][c] + d[r][c];
-          v[r * NC + c] = eh[r][c] + el[r][c];
+          v[r * NC + c] = marked(eh[r][c], el[r][c]);
         }
       }
 #pragma unroll
@@ -400,14 +450,17 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
       }
       if ((hops & (uint64_t)(kRenorm - 1)) == 0) {
         // Fast2Sum: z = fl(hi + lo) - hi is exact and hi + z = fl(hi + lo), so the pair
-        // keeps its sum while hi absorbs lo (written as updates of hi and lo in place)
+        // keeps its sum while hi absorbs lo (written as updates of hi and lo in place); the
+        // occupation bit is then put back into hi
 #pragma unroll
         for (int r = 0; r < RPW; ++r) {
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
+            const uint32_t n = __float_as_uint(eh[r][c]) & 1u;
             const float z = (eh[r][c] + el[r][c]) - eh[r][c];
             el[r][c] = el[r][c] - z;
             eh[r][c] = eh[r][c] + z;
+            set_mark(eh[r][c], el[r][c], n);
           }
         }
       }

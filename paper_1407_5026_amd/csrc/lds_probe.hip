@@ -1,6 +1,7 @@
 // lds_probe.hip -- throughput of the gfx950 units the hop kernels use, for the roofline
-// denominators: LDS reads of 4/8/16 bytes per lane, LDS writes of 4 bytes, the hop
-// kernel's update pattern (per lane 32 table reads in pairs and 16 value stores), FP32
+// denominators: LDS reads and writes of 4/8/16 bytes per lane, the hop
+// kernel's update pattern (per lane 32 table reads in pairs and 16 value stores, and two
+// table layouts with 16-byte value stores), FP32
 // multiplies, 32x32->64-bit integer multiplies and log2.  One workgroup of 1024 threads per
 // CU; every address stays inside the workgroup's LDS array; loop-carried offsets are opaque
 // to the compiler so that no load is hoisted out of the timed loop.
@@ -79,6 +80,7 @@ __global__ void __launch_bounds__(1024) k_barrier(uint32_t* out, int iters) {
   if (v == 0x12345678u) out[blockIdx.x * 1024 + threadIdx.x] = 1;
 }
 
+template <int W>  // dwords per lane and store: 1, 2, 4
 __global__ void __launch_bounds__(1024) k_write(uint32_t* out, int iters) {
   __shared__ __align__(16) uint32_t buf[kWords];
   uint32_t v = threadIdx.x;
@@ -86,7 +88,14 @@ __global__ void __launch_bounds__(1024) k_write(uint32_t* out, int iters) {
     const int off = opaque_int((it & 1) * 64);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      buf[(threadIdx.x + u * 1024 + off) & (kWords - 1)] = v;
+      const int a = (threadIdx.x * W + u * 1024 * W + off) & (kWords - 1);  // lane-consecutive
+      if constexpr (W == 1) {
+        buf[a] = v;
+      } else if constexpr (W == 2) {
+        *(uint2*)&buf[a & ~1] = make_uint2(v, v + 1);
+      } else {
+        *(uint4*)&buf[a & ~3] = make_uint4(v, v + 1, v + 2, v + 3);
+      }
       v += 1;
     }
   }
@@ -123,6 +132,102 @@ __global__ void __launch_bounds__(1024) k_update(uint32_t* out, int iters) {
         acc[2 * r + c] += d[2 * r + c];
         sm[ev + r * 2048 + c * 64] = acc[2 * r + c];
       }
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s += acc[k];
+  if (s == 1.2345f) out[blockIdx.x * 1024 + threadIdx.x] = 1;
+}
+
+typedef float probe_f4 __attribute__((ext_vector_type(4)));
+
+// The update with 16-byte value stores (four per lane, chunk-major) and two table layouts at
+// L = 128.  rows: table rows 68 floats wide by raw row difference, two folded columns per
+// lane, rows 16 apart read in pairs (16 two-address reads per lane).  pairs: per column pair
+// (c, 64 - c) and row, two floats side by side; a lane's 8 rows (one residue class mod 16)
+// are 8 consecutive pairs, read as 4 double-pair reads per base (8 per lane).
+// cols: the table column-major (260 floats per folded column, raw row difference inside), a
+// wave owning 8 consecutive rows: a lane's 8 rows per column are 8 consecutive floats, read
+// as three aligned 16-byte loads (12 per lane).
+template <int LAYOUT, bool STORES = true>  // 0 rows, 1 pairs, 2 cols; STORES off: reads only
+__global__ void __launch_bounds__(1024) k_update_layout(uint32_t* out, int iters) {
+  extern __shared__ __align__(16) float sm[];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < kUpdWords; k += 1024) sm[k] = k * 1e-3f;
+  __syncthreads();
+  float acc[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+  for (int it = 0; it < iters; ++it) {
+    const int yj = it & 127, yi = (it * 5 + 3) & 127, xj = (it * 7) & 127, xi = (it * 11 + 1) & 127;
+    const int dj = (lane - xj) & 127, di = (lane - xi) & 127;
+    const int cj = dj < 128 - dj ? dj : 128 - dj, ci = di < 128 - di ? di : 128 - di;  // 0..64
+    float d[16];
+    if constexpr (LAYOUT == 2) {
+      const int dj1 = (lane + 64 - xj) & 127, di1 = (lane + 64 - xi) & 127;
+      const int cj1 = dj1 < 128 - dj1 ? dj1 : 128 - dj1, ci1 = di1 < 128 - di1 ? di1 : 128 - di1;
+      const int sj = 8 * wid - yj + 128, si = 8 * wid - yi + 128;  // 1..248
+      // largest index 16384 + 64 * 260 + 248 + 11 = 33283 < kUpdWords
+      const int aj0 = opaque_int((16384 + cj * 260 + sj) >> 2) * 4, aj1 = opaque_int((16384 + cj1 * 260 + sj) >> 2) * 4;
+      const int ai0 = opaque_int((16384 + ci * 260 + si) >> 2) * 4, ai1 = opaque_int((16384 + ci1 * 260 + si) >> 2) * 4;
+      float fj0[12], fj1[12], fi0[12], fi1[12];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const probe_f4 a = *(const probe_f4*)&sm[aj0 + 4 * k], b = *(const probe_f4*)&sm[aj1 + 4 * k];
+        const probe_f4 c = *(const probe_f4*)&sm[ai0 + 4 * k], e = *(const probe_f4*)&sm[ai1 + 4 * k];
+        fj0[4 * k] = a.x; fj0[4 * k + 1] = a.y; fj0[4 * k + 2] = a.z; fj0[4 * k + 3] = a.w;
+        fj1[4 * k] = b.x; fj1[4 * k + 1] = b.y; fj1[4 * k + 2] = b.z; fj1[4 * k + 3] = b.w;
+        fi0[4 * k] = c.x; fi0[4 * k + 1] = c.y; fi0[4 * k + 2] = c.z; fi0[4 * k + 3] = c.w;
+        fi1[4 * k] = e.x; fi1[4 * k + 1] = e.y; fi1[4 * k + 2] = e.z; fi1[4 * k + 3] = e.w;
+      }
+      // the kernel picks 8 of the 12 floats by a uniform shift; here every float is used
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        d[k] = (fj0[k] - fi0[k]) + (fj0[k + 4] - fi0[k + 4]);
+        d[8 + k] = (fj1[k] - fi1[k]) + (fj1[k + 4] - fi1[k + 4]);
+      }
+    } else if constexpr (LAYOUT == 1) {
+      // pair column min(c, 64 - c) in 0..32, 516 floats each; start pair in 0..248
+      const int pj = cj < 64 - cj ? cj : 64 - cj, pi = ci < 64 - ci ? ci : 64 - ci;
+      const int bj = wid - yj + 128, bi = wid - yi + 128;  // 1..143
+      const int aj = opaque_int(16384 + pj * 516 + 2 * ((bj & 15) * 16 + (bj >> 4)));
+      const int ai = opaque_int(16384 + pi * 516 + 2 * ((bi & 15) * 16 + (bi >> 4)));
+      // largest index 16384 + 32 * 516 + 2 * 248 + 15 = 33407 < kUpdWords
+      const float2* qj = (const float2*)&sm[aj];
+      const float2* qi = (const float2*)&sm[ai];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float2 vj = qj[k], vi = qi[k];
+        d[2 * k] = vj.x - vi.x;
+        d[2 * k + 1] = vj.y - vi.y;
+      }
+    } else {
+      const int dj1 = (lane + 64 - xj) & 127, di1 = (lane + 64 - xi) & 127;
+      const int cj1 = dj1 < 128 - dj1 ? dj1 : 128 - dj1, ci1 = di1 < 128 - di1 ? di1 : 128 - di1;
+      const int rj = 16384 + (wid - yj + 128) * 68, ri = 16384 + (wid - yi + 128) * 68;
+      const int aj0 = opaque_int(rj + cj), aj1 = opaque_int(rj + cj1);
+      const int ai0 = opaque_int(ri + ci), ai1 = opaque_int(ri + ci1);
+      // largest index 16384 + 143 * 68 + 64 + 7 * 1088 = 33788 < kUpdWords
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        d[2 * r] = sm[aj0 + r * 1088] - sm[ai0 + r * 1088];
+        d[2 * r + 1] = sm[aj1 + r * 1088] - sm[ai1 + r * 1088];
+      }
+    }
+    const int ev = opaque_int(wid * 256 + lane) * 4;  // largest 15360 + 252 + 768 + 3 < 16384
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      probe_f4 w;
+      acc[4 * q] += d[4 * q];
+      acc[4 * q + 1] += d[4 * q + 1];
+      acc[4 * q + 2] += d[4 * q + 2];
+      acc[4 * q + 3] += d[4 * q + 3];
+      w.x = acc[4 * q];
+      w.y = acc[4 * q + 1];
+      w.z = acc[4 * q + 2];
+      w.w = acc[4 * q + 3];
+      if constexpr (STORES) *(probe_f4*)&sm[ev + 256 * q] = w;
     }
   }
   float s = 0.f;
@@ -197,6 +302,11 @@ int main() {
   CHK(hipEventCreate(&e0));
   CHK(hipEventCreate(&e1));
   CHK(hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
+  CHK(hipFuncSetAttribute((const void*)k_update_layout<0>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
+  CHK(hipFuncSetAttribute((const void*)k_update_layout<1>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
+  CHK(hipFuncSetAttribute((const void*)k_update_layout<2>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
+  CHK(hipFuncSetAttribute((const void*)k_update_layout<0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
+  CHK(hipFuncSetAttribute((const void*)k_update_layout<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
   const int iters = 20000;
   float ms = 0.f;
   auto timed = [&](auto launch) -> int {
@@ -224,12 +334,29 @@ int main() {
               ms * 1e-3 * clk / ((double)iters * 4 * 16));
   if (timed([&] { hipLaunchKernelGGL(k_barrier, g, b, 0, 0, out, iters); })) return 1;
   std::printf("s_barrier, 16 waves           %8.3f ms  %7.1f clk per barrier\n", ms, ms * 1e-3 * clk / iters);
-  if (timed([&] { hipLaunchKernelGGL(k_write, g, b, 0, 0, out, iters); })) return 1;
+  if (timed([&] { hipLaunchKernelGGL(k_write<1>, g, b, 0, 0, out, iters); })) return 1;
   std::printf("ds_write_b32  %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 4));
+  if (timed([&] { hipLaunchKernelGGL(k_write<2>, g, b, 0, 0, out, iters); })) return 1;
+  std::printf("ds_write_b64  %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 8));
+  if (timed([&] { hipLaunchKernelGGL(k_write<4>, g, b, 0, 0, out, iters); })) return 1;
+  std::printf("ds_write_b128 %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 16));
   const int upd_iters = iters / 8;
   if (timed([&] { hipLaunchKernelGGL(k_update, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
   std::printf("update        %8.3f ms  %7.1f B/clk  %6.0f clk per pass (32 reads + 16 stores per lane)\n", ms,
               per_cu((double)ncu * 1024 * upd_iters * 48 * 4), ms * 1e-3 * clk / upd_iters);
+  if (timed([&] { hipLaunchKernelGGL(k_update_layout<0>, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
+  std::printf("update, row table    %8.3f ms  %6.0f clk per pass (16 paired 4-byte reads, 4 16-byte stores per lane)\n",
+              ms, ms * 1e-3 * clk / upd_iters);
+  if (timed([&] { hipLaunchKernelGGL(k_update_layout<1>, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
+  std::printf("update, pair table   %8.3f ms  %6.0f clk per pass (8 paired 8-byte reads, 4 16-byte stores per lane)\n",
+              ms, ms * 1e-3 * clk / upd_iters);
+  if (timed([&] { hipLaunchKernelGGL(k_update_layout<2>, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
+  std::printf("update, column table %8.3f ms  %6.0f clk per pass (12 16-byte reads, 4 16-byte stores per lane)\n",
+              ms, ms * 1e-3 * clk / upd_iters);
+  if (timed([&] { hipLaunchKernelGGL((k_update_layout<0, false>), g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
+  std::printf("update reads only, row table    %8.3f ms  %6.0f clk per pass\n", ms, ms * 1e-3 * clk / upd_iters);
+  if (timed([&] { hipLaunchKernelGGL((k_update_layout<2, false>), g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
+  std::printf("update reads only, column table %8.3f ms  %6.0f clk per pass\n", ms, ms * 1e-3 * clk / upd_iters);
   const double wave_ops = (double)ncu * 16 * iters * 64;  // wave instructions per kernel
   if (timed([&] { hipLaunchKernelGGL(k_fmul, g, b, 0, 0, (float*)out, iters); })) return 1;
   std::printf("v_mul_f32     %8.3f ms  %7.2f wave instr/clk\n", ms, wave_ops / (ms * 1e-3) / ncu / clk);
