@@ -72,7 +72,7 @@ struct Rep {
   int32_t a, b, r2;
 };
 
-int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, HostTables& t) {
+int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, int32_t fx_waves, HostTables& t) {
   const double rc = d.rc, xi = d.xi;
   const int32_t L = d.L, N = L * L;
   std::vector<Rep> reps;
@@ -165,11 +165,11 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, Hos
       t.tab64[(size_t)ay * H1 + ax] = r2 == 0 ? 0.0 : 1.0 / std::sqrt((double)r2);
     }
   const size_t nk = layout == kTri ? (size_t)tri_entries(H)
-                    : layout == kRaw ? (size_t)fx_tab_entries(L) : layout == kBig ? 0 : (size_t)full_entries(H);
+                    : layout == kRaw ? (size_t)fx_tab_entries(L, fx_waves) : layout == kBig ? 0 : (size_t)full_entries(H);
   std::vector<double> k64(nk, 0.0);
   if (layout == kRaw) {
     // row b = dy + L, column u = folded |dx| (zero beyond L/2)
-    const int32_t Pp = fx_pitch(L);
+    const int32_t Pp = fx_pitch(L, fx_waves);
     for (int32_t b = 0; b < 2 * L; ++b) {
       const int32_t a = std::abs(b - L), ay = std::min(a, L - a);
       for (int32_t u = 0; u < H1; ++u) k64[(size_t)b * Pp + u] = t.tab64[(size_t)ay * H1 + u];
@@ -290,7 +290,9 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (p.precision != CG_FP64 && p.precision != CG_FP32_REFRESH)
     return set_err(CG_EINVAL, "precision=%d", o->precision);
   p.block = o->block ? o->block : 1024;
-  if (p.block != 1024) return set_err(CG_EINVAL, "block=%d (the hop kernel runs 1024 threads per sample)", o->block);
+  if (p.block != 1024 && p.block != 512)
+    return set_err(CG_EINVAL, "block=%d (the hop kernels run 1024 threads per sample, the exact-geometry "
+                   "kernel also 512)", o->block);
   // M: the paper's parallel width, used for the iteration count p = ceil(m / M); the kernel
   // evaluates labels in chunks of 1024 U (the executed hops do not depend on either)
   p.M = o->M ? o->M : 1024;
@@ -364,13 +366,15 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     same_L = same_L && s[b].L == s[0].L;
     max_orb = std::max(max_orb, count_orbits(s[b].rc));
   }
-  const int32_t need_fx = fx_lds(s[0].L, max_orb).total;
+  const int32_t need_fx = fx_lds(s[0].L, max_orb, p.block / 64).total;
   const bool fx_ok = !p.big && p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
                      need_fx <= lds_cap;
   p.use_fx = fx_ok && (p.variant == 0 || p.variant == 3);
   if (p.variant == 3 && !p.use_fx)
     return set_err(CG_EINVAL, "variant 3 (exact-geometry kernel) needs the FP32 form, one L in {64, 128} "
                    "for all samples and %d bytes of LDS", need_fx);
+  if (p.block != 1024 && !p.use_fx)
+    return set_err(CG_EINVAL, "block=%d needs the exact-geometry kernel (FP32 form, one L in {64, 128})", p.block);
   // automatic choice otherwise: two barriers (measured faster at L = 128: 81e6 vs 75e6 hops/s)
   p.use_db = p.precision == CG_FP32_REFRESH && max_L_all <= 128 && db_fits && p.variant == 2;
   if (p.variant == 2 && !p.use_db)
@@ -411,7 +415,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
     const int32_t ntab = p.layout == kTri ? tri_entries(H)
-                         : p.layout == kRaw ? fx_tab_entries(L) : p.layout == kBig ? 0 : full_entries(H);
+                         : p.layout == kRaw ? fx_tab_entries(L, p.block / 64) : p.layout == kBig ? 0 : full_entries(H);
     const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
     const bool bigl = p.layout == kBig, sel16 = p.layout == kRaw || bigl;
     max_L = std::max(max_L, L);
@@ -508,14 +512,21 @@ BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t* grid) {
   return U == 1 ? pick_big_uc<1, 0>(L, grid) : pick_big_uc<2, 0>(L, grid);
 }
 
+// chunks of 1024 U labels: U labels per thread with 16 waves, 2 U with 8
 template <int CLOCK>
-HopFn pick_fx(int32_t U, int32_t NC) {
-  if (NC == 1) return U == 1 ? k_hops_fx<64, 1, CLOCK> : k_hops_fx<64, 2, CLOCK>;
-  return U == 1 ? k_hops_fx<128, 1, CLOCK> : k_hops_fx<128, 2, CLOCK>;
+HopFn pick_fx(int32_t U, int32_t NC, int32_t NW) {
+  if (NW == 8) {
+    if (NC == 1) return U == 1 ? k_hops_fx<64, 2, CLOCK, 8> : k_hops_fx<64, 4, CLOCK, 8>;
+    return U == 1 ? k_hops_fx<128, 2, CLOCK, 8> : k_hops_fx<128, 4, CLOCK, 8>;
+  }
+  if (NC == 1) return U == 1 ? k_hops_fx<64, 1, CLOCK, 16> : k_hops_fx<64, 2, CLOCK, 16>;
+  return U == 1 ? k_hops_fx<128, 1, CLOCK, 16> : k_hops_fx<128, 2, CLOCK, 16>;
 }
 
-HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock) {
-  if (layout == kRaw) return clock == CG_CLOCK_GAUSS ? pick_fx<1>(U, NC) : pick_fx<0>(U, NC);
+HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
+              int32_t block) {
+  if (layout == kRaw)
+    return clock == CG_CLOCK_GAUSS ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);
   if (db) return pick_db(U, NC, exact);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
@@ -779,7 +790,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
       return set_err(CG_EHIP, "whole-GPU kernel set-up: %s", hipGetErrorString(e));
     }
   } else {
-    c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock);
+    c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block);
   }
 
   auto fail = [&](int code) {
@@ -793,7 +804,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     const cg_sample_desc& d = samples[b];
     const SampleLayout& q = p.sl[b];
     HostTables t;
-    rc = build_tables(d, p.layout, p.precision, t);
+    rc = build_tables(d, p.layout, p.precision, p.block / 64, t);
     if (rc != CG_OK) return fail(rc);
     const int32_t L = d.L, N = L * L;
     const uint32_t magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)L - 1) / (uint64_t)L);
@@ -829,7 +840,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.NW = (N + 31) / 32;
     s.n_orb = t.n_orb;
     s.n_vec = t.n_vec;
-    s.ntab = p.layout == kTri ? tri_entries(t.H) : p.layout == kRaw ? fx_tab_entries(L) : full_entries(t.H);
+    s.ntab = p.layout == kTri ? tri_entries(t.H) : p.layout == kRaw ? fx_tab_entries(L, p.block / 64) : full_entries(t.H);
     s.nblk = (N + kInitBlock - 1) / kInitBlock;
     s.log_cap = p.log_cap;
     s.layout = p.layout;

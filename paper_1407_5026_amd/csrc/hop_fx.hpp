@@ -1,13 +1,13 @@
-// hop_fx.hpp -- FP32 hop kernel for lattices that fill the 1024-thread geometry exactly
-// (L = 64 or 128; wave w owns rows w + 16 r, lane the columns lane + 64 c).
+// hop_fx.hpp -- FP32 hop kernel for lattices that fill a workgroup of NW = 16 or 8 waves
+// exactly (L = 64 or 128; wave w owns rows w + NW r, lane the columns lane + 64 c).
 //
 // It runs the same mixed parallel-rejection step as k_hops (section "Hopping conduction in
 // the Coulomb glass", steps 1, 2, 3a-3c, with the labels of a chunk drawn once and re-used
 // after a hop) and executes the same hops, with three changes in how the work is laid out:
 //
 //  * The 1/r table is indexed by the raw row difference b = dy + L in [1, 2L) and the folded
-//    column distance.  In step 3b a lane's table address for its row y = w + 16 r is then a
-//    per-hop base plus 16 r rows, a compile-time offset, so the row terms need neither
+//    column distance.  In step 3b a lane's table address for its row y = w + NW r is then a
+//    per-hop base plus NW r rows, a compile-time offset, so the row terms need neither
 //    scalar nor vector arithmetic.
 //  * A site's FP32 energy is a pair hi + lo.  Step 3b adds the FP32 increment
 //    1/r_lj - 1/r_li to lo, the proposals read fl(hi + lo) from LDS, and every kRenorm hops
@@ -56,22 +56,26 @@ struct FxShared {
   double t;          // Gaussian clock
 };
 
-template <int L>
+template <int L, int NW>
 struct FxGeo {
   static constexpr int LG = L == 64 ? 6 : 7;
   static constexpr int N = L * L;
+  static constexpr int NT = 64 * NW;  // threads
+  static constexpr int LW = NW == 16 ? 4 : 3;
   static constexpr int NC = L / 64;
-  static constexpr int RPW = L / 16;
-  static constexpr int P = fx_pitch(L);
+  static constexpr int RPW = L / NW;
+  static constexpr int P = fx_pitch(L, NW);
   static constexpr int SPL = RPW * NC;  // sites per lane
   static_assert(L == 64 || L == 128, "exact geometry: L = 64 or 128");
-  // LDS word of site (x, y)'s energy value.  The owner is wave y & 15, lane x & 63, slot
-  // s = (y >> 4) NC + (x >> 6); each wave's 64 SPL words are laid out as [s / 4][lane][s % 4],
+  static_assert(NW == 16 || NW == 8, "16 or 8 waves");
+  static_assert(SPL % 4 == 0 && SPL <= 32, "whole 16-byte chunks, at most 32 sites per lane");
+  // LDS word of site (x, y)'s energy value.  The owner is wave y % NW, lane x & 63, slot
+  // s = (y / NW) NC + (x >> 6); each wave's 64 SPL words are laid out as [s / 4][lane][s % 4],
   // so the wave stores its values with SPL / 4 16-byte stores, each covering 1024
   // contiguous bytes (lane-consecutive: no bank conflicts)
   __device__ static int ev_slot(int x, int y) {
-    const int s = (y >> 4) * NC + (x >> 6);
-    return (y & 15) * 64 * SPL + (s >> 2) * 256 + (x & 63) * 4 + (s & 3);
+    const int s = (y >> LW) * NC + (x >> 6);
+    return (y & (NW - 1)) * 64 * SPL + (s >> 2) * 256 + (x & 63) * 4 + (s & 3);
   }
 };
 
@@ -120,10 +124,10 @@ struct FxConst {
   float Ef, mTln2;       // E and -T ln 2 in FP32
 };
 
-template <int L, int U>
+template <int L, int U, int NW>
 __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C, uint32_t lds0,
                                         const FxLds& lo, FxLabel (&lb)[U]) {
-  using G = FxGeo<L>;
+  using G = FxGeo<L, NW>;
   const uint32_t guide = lds0 + lo.guide, thr = lds0 + lo.thr, vec8 = lds0 + lo.vec8;
   const uint32_t ev = lds0 + lo.ev;
   const int last = C.last;
@@ -160,12 +164,12 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C
 
 // CLOCK = 0: deterministic clock t = s_last / Gamma; 1: Gaussian increments (step 3c), the
 // only per-hop call, kept out of the deterministic instance.
-template <int L, int U, int CLOCK>
-__global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ samples,
+template <int L, int U, int CLOCK, int NW>
+__global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict__ samples,
                                                   const int32_t* __restrict__ order, RunArgs ra) {
-  using G = FxGeo<L>;
-  constexpr int NW = 16, NC = G::NC, RPW = G::RPW, P = G::P, SPL = G::SPL;
-  constexpr uint32_t M = 1024u * U;
+  using G = FxGeo<L, NW>;
+  constexpr int NT = G::NT, NC = G::NC, RPW = G::RPW, P = G::P, SPL = G::SPL;
+  constexpr uint32_t M = (uint32_t)NT * U;
   constexpr int kRenorm = 16;
   const DevSample& S = samples[order[blockIdx.x]];
   SampleState* __restrict__ gs = S.st;
@@ -194,7 +198,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
   int32_t status = 0;
 
   extern __shared__ __align__(16) uint8_t smem[];
-  const FxLds lo = fx_lds(L, S.n_orb);
+  const FxLds lo = fx_lds(L, S.n_orb, NW);
   const uint32_t lds0 = lds_addr_of(smem);
   float* __restrict__ ev = (float*)(smem + lo.ev);
   uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
@@ -219,12 +223,12 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     }
     const uint4* __restrict__ gt = (const uint4*)S.tabk;
     uint4* __restrict__ st = (uint4*)(smem + lo.tab);
-    for (int k = tid; k < fx_tab_entries(L) / 4; k += 1024) st[k] = gt[k];
+    for (int k = tid; k < fx_tab_entries(L, NW) / 4; k += NT) st[k] = gt[k];
   }
-  for (int k = tid; k < G::N / 32; k += 1024) occ[k] = S.occ[k];
-  for (int k = tid; k < S.n_orb; k += 1024) ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
-  for (int k = tid; k < kGuideSize; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
-  for (int k = tid; k < S.n_orb * 8; k += 1024) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
+  for (int k = tid; k < G::N / 32; k += NT) occ[k] = S.occ[k];
+  for (int k = tid; k < S.n_orb; k += NT) ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
+  for (int k = tid; k < kGuideSize; k += NT) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
+  for (int k = tid; k < S.n_orb * 8; k += NT) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
   if (tid < kMaxWaves) info[tid] = make_uint4(0u, 0u, 0u, ~0u);  // no round has this tag
   if (tid == 0) {
     sh->theta = 0u;
@@ -245,7 +249,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
   int32_t* __restrict__ log_from = S.log_from;
   int32_t* __restrict__ log_to = S.log_to;
   const uint64_t s_end = uni((ra.time_mode && CLOCK == 0) ? label_at_time(t_end, Gamma) : (uint64_t)0);
-  // this lane's energy values (row wid + 16 r, column lane + 64 c at slot s = r NC + c): chunk
+  // this lane's energy values (row wid + NW r, column lane + 64 c at slot s = r NC + c): chunk
   // s / 4 at ev_lane + 1024 (s / 4)
   const uint32_t ev_lane = opaque(lds0 + lo.ev + 4u * (uint32_t)(wid * 64 * SPL + lane * 4));
   constexpr int kRowTab = NW * P * 4;
@@ -277,7 +281,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
 #pragma unroll
         for (int k = 0; k < U; ++k) lb[k] = lbn[k];
       } else {
-        draw_fx<L, U>(base, tid, C, lds0, lo, lb);
+        draw_fx<L, U, NW>(base, tid, C, lds0, lo, lb);
       }
       cached = true;
       CG_MARK(tc0)
@@ -310,7 +314,8 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
       }
     }
     // the wave's lowest accepting lane publishes its label in the wave's record, tagged with
-    // the round; after the barrier lanes 0..15 read the 16 records and the round's winner is
+    // the round; after the barrier lanes 0..15 read the 16 records (waves beyond NW never
+    // write theirs, whose initial tag no round carries) and the round's winner is
     // the lowest wave whose record carries this round's tag (keys grow with the thread
     // index).  A record is rewritten only by its own wave: in a later round, which only
     // happens before another wave reads it for this round if this round executed no hop
@@ -373,12 +378,11 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
       if (CLOCK != 0) sh->t = sh->t + gauss_dt(hops, m, C.sid, C.k0, C.k1, Gamma);
     }
     logged += logged < log_cap ? 1 : 0;
-    // the owners of i and j move their occupation marks: site (x, y) is slot (y >> 4) NC +
-    // (x >> 6) of lane x & 63 in wave y & 15; the slot index is wave-uniform, so a short
+    // the owners of i and j move their occupation marks: site (x, y) is slot (y / NW) NC +
+    // (x >> 6) of lane x & 63 in wave y % NW; the slot index is wave-uniform, so a short
     // branch tree picks the register
     {
       const int xi = hi & (L - 1), yi = hi >> G::LG, xj = hj & (L - 1), yj = hj >> G::LG;
-      static_assert(SPL <= 16, "slot switch covers 16 slots");
 #define CG_SLOT(k)                                                                   \
   case k:                                                                            \
     if constexpr (k < SPL) {                                                         \
@@ -389,15 +393,17 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
   switch (sl) {                                                                      \
     CG_SLOT(0) CG_SLOT(1) CG_SLOT(2) CG_SLOT(3) CG_SLOT(4) CG_SLOT(5) CG_SLOT(6)     \
     CG_SLOT(7) CG_SLOT(8) CG_SLOT(9) CG_SLOT(10) CG_SLOT(11) CG_SLOT(12) CG_SLOT(13) \
-    CG_SLOT(14) CG_SLOT(15) default: break;                                          \
+    CG_SLOT(14) CG_SLOT(15) CG_SLOT(16) CG_SLOT(17) CG_SLOT(18) CG_SLOT(19) CG_SLOT(20) \
+    CG_SLOT(21) CG_SLOT(22) CG_SLOT(23) CG_SLOT(24) CG_SLOT(25) CG_SLOT(26) CG_SLOT(27) \
+    CG_SLOT(28) CG_SLOT(29) CG_SLOT(30) CG_SLOT(31) default: break;                  \
   }
-      if (wid == (yi & 15) && lane == (xi & 63)) {
+      if (wid == (yi & (NW - 1)) && lane == (xi & 63)) {
         const uint32_t n = 0u;
-        CG_SLOTS((yi >> 4) * NC + (xi >> 6))
+        CG_SLOTS((yi >> G::LW) * NC + (xi >> 6))
       }
-      if (wid == (yj & 15) && lane == (xj & 63)) {
+      if (wid == (yj & (NW - 1)) && lane == (xj & 63)) {
         const uint32_t n = 1u;
-        CG_SLOTS((yj >> 4) * NC + (xj >> 6))
+        CG_SLOTS((yj >> G::LW) * NC + (xj >> 6))
       }
 #undef CG_SLOTS
 #undef CG_SLOT
@@ -405,7 +411,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     CG_MARK(tc2)
 
     // step 3b on the owned sites: lo += 1/r_lj - 1/r_li, LDS value fl(hi + lo).  Row
-    // y = wid + 16 r of the table for origin row y0 is row wid - y0 + L + 16 r.  All table
+    // y = wid + NW r of the table for origin row y0 is row wid - y0 + L + NW r.  All table
     // loads are issued before the first store.
     {
       const int xi = hi & (L - 1), yi = hi >> G::LG, xj = hj & (L - 1), yj = hj >> G::LG;
@@ -428,7 +434,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
       // while the table loads are in flight: draw the next chunk if it is not drawn yet
       if (next_base != base + M) {
         next_base = base + M;
-        draw_fx<L, U>(next_base, tid, C, lds0, lo, lbn);
+        draw_fx<L, U, NW>(next_base, tid, C, lds0, lo, lbn);
       }
       float v[SPL];
 #pragma unroll
@@ -489,7 +495,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx(const DevSample* __restrict__ 
     }
   }
   __syncthreads();
-  for (int k = tid; k < G::N / 32; k += 1024) S.occ[k] = occ[k];
+  for (int k = tid; k < G::N / 32; k += NT) S.occ[k] = occ[k];
   if (tid == 0) {
     gs->hops = hops;
     gs->s_last = s_last;

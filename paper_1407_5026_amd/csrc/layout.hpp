@@ -128,13 +128,16 @@ __host__ __device__ inline HopLds hop_lds(int32_t N, int32_t NW, int32_t ntab, i
   return o;
 }
 
-// Exact-geometry FP32 kernel (L = 64 or 128, every thread owns L*L/1024 sites).
-// Its 1/r table holds row b in [0, 2L) for the raw row difference dy = b - L and column u
-// for the folded column distance u <= L/2: entry 1/sqrt(fold(b - L)^2 + u^2), 0 at the
-// origin and beyond u = L/2.  The row pitch is a multiple of 4 floats so that a wave's
-// rows, 16 apart, are a multiple of 256 bytes apart.
-__host__ __device__ constexpr int32_t fx_pitch(int32_t L) { return ((L / 2 + 1) + 3) & ~3; }
-__host__ __device__ constexpr int32_t fx_tab_entries(int32_t L) { return 2 * L * fx_pitch(L); }
+// Exact-geometry FP32 kernel (L = 64 or 128, NW waves of 64 lanes; every thread owns
+// L*L/(64 NW) sites).  Its 1/r table holds row b in [0, 2L) for the raw row difference
+// dy = b - L and column u for the folded column distance u <= L/2: entry
+// 1/sqrt(fold(b - L)^2 + u^2), 0 at the origin and beyond u = L/2.  The row pitch is a
+// multiple of 64 / NW floats so that a wave's rows, NW apart, are a multiple of 256 bytes
+// apart (one two-row read each).
+__host__ __device__ constexpr int32_t fx_pitch(int32_t L, int32_t NW = 16) {
+  return ((L / 2 + 1) + 64 / NW - 1) / (64 / NW) * (64 / NW);
+}
+__host__ __device__ constexpr int32_t fx_tab_entries(int32_t L, int32_t NW = 16) { return 2 * L * fx_pitch(L, NW); }
 
 struct FxLds {
   int32_t ev, occ, tab, thr, guide, ctrl, info, vec8, total;
@@ -142,12 +145,12 @@ struct FxLds {
 
 // LDS of the exact-geometry kernel: energy values, occupation, table, thresholds, guide,
 // control words, per-wave winner records, displacement table.
-__host__ __device__ inline FxLds fx_lds(int32_t L, int32_t n_orb) {
+__host__ __device__ inline FxLds fx_lds(int32_t L, int32_t n_orb, int32_t NW = 16) {
   FxLds o;
   int32_t b = 0;
   o.ev = b;    b = align16(b + L * L * 4);
   o.occ = b;   b = align16(b + L * L / 8);
-  o.tab = b;   b = align16(b + fx_tab_entries(L) * 4);
+  o.tab = b;   b = align16(b + fx_tab_entries(L, NW) * 4);
   o.thr = b;   b = align16(b + n_orb * 4);
   o.guide = b; b = align16(b + kGuideSize * 2);
   o.ctrl = b;  b = align16(b + 64);

@@ -318,3 +318,26 @@ def test_fp32_kernels_agree(other):
         assert first >= 100
         assert int(b2.occupation(k).sum()) == s.n_e
         assert b2.stats(k)["max_drift"] <= 1e-5
+
+
+@pytest.mark.parametrize("L", [64, 128])
+def test_fp32_eight_wave_kernel_is_bitwise_the_sixteen_wave_one(L):
+    """The exact-geometry kernel with 8 waves per sample (block=512) performs the same FP32
+    operations per site as with 16 waves: identical hops, energies and drift."""
+    cg = require_gpu()
+    from workloads import headline
+
+    samples = headline(3) if L == 128 else [Sample(64, 2048, 1.0, 1.0, 8.0, 0.05, 0.01, 4, b) for b in range(3)]
+    hops = 1500
+    kw = dict(precision=cg.CG_FP32_REFRESH, K_refresh=1024, log_hops=hops, variant=3)
+    b16 = _batch(cg, samples, block=1024, **kw)
+    b8 = _batch(cg, samples, block=512, **kw)
+    b16.run_hops(hops)
+    b8.run_hops(hops)
+    for k in range(len(samples)):
+        for a, b in zip(b16.hop_log(k), b8.hop_log(k)):
+            assert np.array_equal(a, b)
+        assert np.array_equal(b16.energies(k), b8.energies(k))
+        s16, s8 = b16.stats(k), b8.stats(k)
+        assert s16["max_drift"] == s8["max_drift"] and s16["hops"] == s8["hops"] == hops
+    say(f"L={L}: 8-wave and 16-wave kernels identical over {hops} hops")
