@@ -27,8 +27,8 @@ sys.path.insert(0, ROOT)
 
 # LDS bandwidth of the chip: 256 CUs x 224 B/clk x 2.4 GHz, the best rate the unit probe
 # (python -m paper_1407_5026_amd.probe) measures on MI355X, with 16-byte ds_read_b128; 4-byte
-# reads reach 65 B/clk and 4-byte writes 52 B/clk, because each LDS instruction occupies the
-# CU's LDS pipe for ~4-5 cycles whatever its width
+# reads reach 65 B/clk (each LDS read instruction occupies the CU's LDS pipe for ~4-5 cycles
+# whatever its width), and writes at most ~72 B/clk at any width
 LDS_PEAK_GBS = 256 * 224 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hops_fx_l128_b256_traffic.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1407_5026_amd", "csrc", f) for f in ("hop_fx.hpp", "kernels.hpp", "layout.hpp")]
@@ -255,7 +255,7 @@ def main() -> int:
         "fp32_window_hops_per_s": [round(v) for v in r32["windows"]],
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": f"k_hops_fx<128, {1 if args.M <= 1024 else 2}>", "bytes_per_hop": bytes_per_hop,
+                     "kernel": f"k_hops_fx<128, {1 if args.M <= 1024 else 2}, 0, 16>", "bytes_per_hop": bytes_per_hop,
                      "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
     }
     if r64 is not None:
