@@ -168,6 +168,21 @@ int cg_get_current(cg_ctx* ctx, int32_t sample, double* t, int64_t* P, double* s
 int cg_get_hop_log(cg_ctx* ctx, int32_t sample, uint64_t* labels, int32_t* from, int32_t* to,
                    int64_t cap, int64_t* count);
 
+/* Checkpoint of one sample (the state the paper's algorithm carries from hop to hop: the
+ * occupation of Eq. 1, the local energies of Eq. 2, the clock, the next label and the
+ * counters; section "Hopping conduction in the Coulomb glass", steps 1-3).
+ * cg_save with host_blob == NULL stores the size in *bytes; otherwise *bytes is the buffer
+ * size (CG_ENOSPC if too small) and receives the bytes written.  The blob is a header
+ * (magic "CGKMCSV1", version 1, precision, the sample's L, n_e, W, xi, rc, seed, sample id
+ * and current T and E), the sample state, the occupation words and the energies (8 bytes
+ * per site: FP64, or the FP32 pair).  cg_load checks the header against sample `sample`
+ * of this context (same precision and sample parameters, exact size; CG_EINVAL
+ * otherwise), restores the state, occupation, energies and T, E, and empties the sample's
+ * hop log; the sample then continues exactly as the saved one would have (the labels are
+ * counter-based).  The caller owns the blob; both calls synchronise the context stream. */
+int cg_save(cg_ctx* ctx, int32_t sample, void* host_blob, size_t* bytes);
+int cg_load(cg_ctx* ctx, int32_t sample, const void* host_blob, size_t bytes);
+
 /* Device time of the hop kernel launches since the last call (ms) and launch count, and
  * the same for refreshes; resets them.  Timing uses HIP events on the context stream; with
  * use_graph, each replay is timed as a whole and added to the hop time. */

@@ -32,6 +32,7 @@ EXPORTS = (
     "cg_arena_bytes", "cg_create", "cg_destroy", "cg_run_hops", "cg_run_time", "cg_refresh",
     "cg_set_TE", "cg_get_occupation", "cg_get_local_energies", "cg_get_phi", "cg_get_stats",
     "cg_get_current", "cg_get_hop_log", "cg_take_kernel_time", "cg_autotune", "cg_last_error",
+    "cg_save", "cg_load",
 )
 
 
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH):
     L.cg_get_current.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_int64), P(C.c_double)]
     L.cg_get_hop_log.argtypes = [vp, C.c_int32, P(C.c_uint64), P(C.c_int32), P(C.c_int32), C.c_int64,
                                  P(C.c_int64)]
+    L.cg_save.argtypes = [vp, C.c_int32, vp, P(C.c_size_t)]
+    L.cg_load.argtypes = [vp, C.c_int32, vp, C.c_size_t]
     L.cg_take_kernel_time.argtypes = [vp, P(C.c_double), P(C.c_int64), P(C.c_double), P(C.c_int64)]
     L.cg_autotune.argtypes = [P(cg_sample_desc), C.c_int32, P(cg_run_opts), vp, C.c_size_t, vp, C.c_int64,
                               C.c_double]
@@ -242,6 +245,19 @@ class Batch:
                                      to.ctypes.data_as(C.POINTER(C.c_int32)), cap, C.byref(cnt)))
         k = cnt.value
         return lab[:k].copy(), fr[:k].copy(), to[:k].copy()
+
+    def save(self, b: int) -> bytes:
+        """Checkpoint of sample b (header, state, occupation, energies) as bytes."""
+        n = C.c_size_t()
+        _check(load().cg_save(self._h, b, None, C.byref(n)))
+        buf = (C.c_uint8 * n.value)()
+        _check(load().cg_save(self._h, b, C.cast(buf, C.c_void_p), C.byref(n)))
+        return bytes(buf[: n.value])
+
+    def load(self, b: int, blob: bytes) -> None:
+        """Restore sample b from a checkpoint written by save() for the same sample."""
+        buf = (C.c_uint8 * len(blob)).from_buffer_copy(blob)
+        _check(load().cg_load(self._h, b, C.cast(buf, C.c_void_p), len(blob)))
 
     def kernel_time(self):
         """(hop-kernel ms, hop launches, refresh ms, refresh launches) since the last call."""

@@ -1234,6 +1234,102 @@ int cg_get_hop_log(cg_ctx* c, int32_t b, uint64_t* labels, int32_t* from, int32_
   return CG_OK;
 }
 
+// Checkpoint blob of one sample: header, the sample state, occupation words, energies.
+struct SaveHeader {
+  char magic[8];  // "CGKMCSV1"
+  uint32_t version, state_bytes;
+  int32_t precision, L, n_e, pad_;
+  double W, xi, rc, T, E;
+  uint64_t seed;
+  uint32_t sample_id, occ_words;
+  uint64_t eps_bytes;
+};
+constexpr char kSaveMagic[8] = {'C', 'G', 'K', 'M', 'C', 'S', 'V', '1'};
+
+size_t save_bytes(const DevSample& s) { return sizeof(SaveHeader) + sizeof(SampleState) + 4 * (size_t)s.NW + 8 * (size_t)s.N; }
+
+int cg_save(cg_ctx* c, int32_t b, void* host_blob, size_t* bytes) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!bytes) return set_err(CG_EINVAL, "null size");
+  const DevSample& s = c->dev[b];
+  const size_t need = save_bytes(s);
+  if (!host_blob) {
+    *bytes = need;
+    return CG_OK;
+  }
+  if (*bytes < need) return set_err(CG_ENOSPC, "checkpoint needs %zu bytes (%zu given)", need, *bytes);
+  const cg_sample_desc& d = c->desc[b];
+  SaveHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kSaveMagic, 8);
+  h.version = 1;
+  h.state_bytes = (uint32_t)sizeof(SampleState);
+  h.precision = c->plan.precision;
+  h.L = d.L;
+  h.n_e = d.n_electrons;
+  h.W = d.W;
+  h.xi = d.xi;
+  h.rc = d.rc;
+  h.T = d.T;
+  h.E = d.E;
+  h.seed = d.seed;
+  h.sample_id = d.sample_id;
+  h.occ_words = (uint32_t)s.NW;
+  h.eps_bytes = 8 * (size_t)s.N;
+  uint8_t* out = (uint8_t*)host_blob;
+  std::memcpy(out, &h, sizeof(h));
+  out += sizeof(h);
+  HIPCHK(hipMemcpyAsync(out, s.st, sizeof(SampleState), hipMemcpyDeviceToHost, c->stream));
+  out += sizeof(SampleState);
+  HIPCHK(hipMemcpyAsync(out, s.occ, 4 * (size_t)s.NW, hipMemcpyDeviceToHost, c->stream));
+  out += 4 * (size_t)s.NW;
+  HIPCHK(hipMemcpyAsync(out, s.eps, h.eps_bytes, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *bytes = need;
+  return CG_OK;
+}
+
+int cg_load(cg_ctx* c, int32_t b, const void* host_blob, size_t bytes) {
+  int rc = sample_ok(c, b);
+  if (rc != CG_OK) return rc;
+  if (!host_blob) return set_err(CG_EINVAL, "null checkpoint");
+  const DevSample& s = c->dev[b];
+  const size_t need = save_bytes(s);
+  if (bytes < sizeof(SaveHeader)) return set_err(CG_EINVAL, "checkpoint of %zu bytes has no header", bytes);
+  SaveHeader h;
+  std::memcpy(&h, host_blob, sizeof(h));
+  const cg_sample_desc& d = c->desc[b];
+  if (std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1 || h.state_bytes != sizeof(SampleState))
+    return set_err(CG_EINVAL, "not a checkpoint of this library version");
+  if (bytes != need || h.occ_words != (uint32_t)s.NW || h.eps_bytes != 8 * (size_t)s.N)
+    return set_err(CG_EINVAL, "checkpoint of %zu bytes does not match sample %d (%zu bytes)", bytes, b, need);
+  if (h.precision != c->plan.precision)
+    return set_err(CG_EINVAL, "checkpoint precision %d, context precision %d", h.precision, c->plan.precision);
+  if (h.L != d.L || h.n_e != d.n_electrons || h.W != d.W || h.xi != d.xi || h.rc != d.rc || h.seed != d.seed ||
+      h.sample_id != d.sample_id)
+    return set_err(CG_EINVAL, "checkpoint is of another sample (L, n_e, W, xi, rc, seed or sample id differ)");
+  SampleState st;
+  const uint8_t* in = (const uint8_t*)host_blob + sizeof(h);
+  std::memcpy(&st, in, sizeof(st));
+  in += sizeof(st);
+  st.logged = 0;  // the hop log is not part of a checkpoint
+  st.grid_bar = 0;
+  st.force_refresh = 0;
+  // the blob's T and E were current when it was written
+  rc = cg_set_TE(c, b, h.T, h.E);
+  if (rc != CG_OK) return rc;
+  HIPCHK(hipMemcpyAsync(s.st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(s.occ, in, 4 * (size_t)s.NW, hipMemcpyHostToDevice, c->stream));
+  in += 4 * (size_t)s.NW;
+  HIPCHK(hipMemcpyAsync(s.eps, in, h.eps_bytes, hipMemcpyHostToDevice, c->stream));
+  // the large-sample kernel's proposals read a mirror of the energies (empty otherwise)
+  if (c->plan.layout == kBig) HIPCHK(hipMemcpyAsync(s.mirror, in, h.eps_bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->lockstep_since = -1;  // this sample's refresh phase may now differ from the others'
+  return CG_OK;
+}
+
 int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, void* arena, size_t arena_bytes,
                 void* hip_stream, int64_t trial_hops, double drift_target) {
   if (!opts) return set_err(CG_EINVAL, "null options");

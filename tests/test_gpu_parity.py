@@ -341,3 +341,47 @@ def test_fp32_eight_wave_kernel_is_bitwise_the_sixteen_wave_one(L):
         s16, s8 = b16.stats(k), b8.stats(k)
         assert s16["max_drift"] == s8["max_drift"] and s16["hops"] == s8["hops"] == hops
     say(f"L={L}: 8-wave and 16-wave kernels identical over {hops} hops")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_checkpoint_restores_exactly(prec):
+    """cg_save / cg_load: a sample saved after 600 hops and loaded into another context (whose
+    copy of the sample is elsewhere in its run) continues exactly as the saved one did: the
+    same next 900 hops, energies, clock, dipole and counters; in the FP64 form the whole
+    trajectory is the oracle's.  Mismatched checkpoints are refused."""
+    cg = require_gpu()
+    samples = [Sample(64, 2048, 1.0, 1.0, 8.0, 0.05, 0.01, 12, b) for b in range(3)]
+    kw = dict(precision=prec, K_refresh=500, log_hops=1500)
+    a = _batch(cg, samples, **kw)
+    a.run_hops(600)
+    blob = a.save(1)
+    a.run_hops(900)
+    b = _batch(cg, samples, **kw)
+    b.run_hops(200)
+    b.load(1, blob)
+    assert len(b.hop_log(1)[0]) == 0
+    b.run_hops(900)
+    la, lb = a.hop_log(1), b.hop_log(1)
+    for x, y in zip(la, lb):
+        assert np.array_equal(x[600:1500], y)
+    assert np.array_equal(a.energies(1), b.energies(1))
+    assert np.array_equal(a.occupation(1), b.occupation(1))
+    sa, sb = a.stats(1), b.stats(1)
+    for k in ("hops", "s_last", "s_scan", "P", "t", "H0", "sum_p", "refreshes", "max_drift"):
+        assert sa[k] == sb[k], k
+    # the other samples of b are untouched by the load
+    assert b.stats(0)["hops"] == 1100
+    if prec == 0:
+        o = oracle_of(samples[1])
+        ol = o.run(1500)
+        full = (np.concatenate([la[0][:600], lb[0]]), np.concatenate([la[1][:600], lb[1]]),
+                np.concatenate([la[2][:600], lb[2]]))
+        assert compare_logs(samples[1], full, ol) == 1500
+    with pytest.raises(cg.CgError):
+        b.load(2, blob)  # another sample
+    with pytest.raises(cg.CgError):
+        b.load(1, blob[:-8])  # truncated
+    other = _batch(cg, samples, precision=1 - prec, K_refresh=500)
+    with pytest.raises(cg.CgError):
+        other.load(1, blob)  # other precision
+    say(f"checkpoint precision={prec}: {len(blob)} bytes, 900 hops after the load identical")

@@ -73,3 +73,26 @@ def test_whole_gpu_kernel_large_lattice(L, hops):
     e = b.energies(0)
     for l in np.concatenate([sites, fr[-4:], to[-4:]]).tolist():
         assert abs(e[l] - lazy.site_eps(l)) <= 1e-10, l
+
+
+def test_whole_gpu_kernel_checkpoint():
+    """cg_save / cg_load on a whole-GPU sample (L = 256): the energies, their mirror and the
+    state come back, and the next hops are the ones the saved run executed."""
+    cg = require_gpu()
+    s = Sample(256, 32768, 1.0, 1.0, 10.0, 0.05, 0.005, 43, 0)
+    say("whole-GPU checkpoint L=256")
+    a = _batch(cg, [s], precision=cg.CG_FP64, log_hops=600)
+    a.run_hops(300)
+    blob = a.save(0)
+    a.run_hops(300)
+    b = _batch(cg, [s], precision=cg.CG_FP64, log_hops=600)
+    b.run_hops(50)
+    b.load(0, blob)
+    b.run_hops(300)
+    la, lb = a.hop_log(0), b.hop_log(0)
+    for x, y in zip(la, lb):
+        assert np.array_equal(x[300:600], y)
+    assert np.array_equal(a.energies(0), b.energies(0))
+    sa, sb = a.stats(0), b.stats(0)
+    for k in ("hops", "s_last", "P", "t", "H0"):
+        assert sa[k] == sb[k], k
