@@ -87,6 +87,8 @@ def lib():
         L.or_acceptance.argtypes = [C.c_void_p]
         L.or_acceptance.restype = C.c_double
         L.or_set_mutation.argtypes = [C.c_int32]
+        L.or_gamma_dt.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_double]
+        L.or_gamma_dt.restype = C.c_double
         _lib = L
     return _lib
 
@@ -102,6 +104,11 @@ def philox(ctr, key) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     lib().or_philox(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(out, C.c_uint32))
     return out
+
+
+def gamma_dt(seed: int, sample_id: int, hop: int, m: int, Gamma: float) -> float:
+    """The exact serial clock's increment for hop `hop` after m proposals (Gamma(m, Gamma))."""
+    return lib().or_gamma_dt(seed, sample_id, hop, m, Gamma)
 
 
 def set_mutation(m: int) -> None:

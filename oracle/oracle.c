@@ -41,7 +41,7 @@ void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3 };
+enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3, TAG_GAMMA = 4 };
 
 static void stream(const or_state* st, uint64_t idx, uint32_t tag, uint32_t w[4]);
 
@@ -278,7 +278,7 @@ static int create(const or_params* p, or_state** out, int32_t lazy) {
   if (p->n_e < 1 || p->n_e >= N) return -1;
   if (!(p->T > 0.0) || !(p->xi > 0.0) || !(p->W >= 0.0)) return -1;
   if (!(p->rc >= 1.0) || !(2.0 * p->rc < (double)p->L)) return -1;
-  if (p->clock_mode != 0 && p->clock_mode != 1) return -1;
+  if (p->clock_mode < 0 || p->clock_mode > 2) return -1;
 
   or_state* st = (or_state*)calloc(1, sizeof(or_state));
   if (!st) return -2;
@@ -451,13 +451,51 @@ static void update_eps(or_state* st, int32_t i, int32_t j) {
     }
 }
 
+/* Exact serial clock: the serial mixed algorithm adds an Exp(Gamma) waiting time
+ * after every proposal, so the m proposals up to and including an executed hop add
+ * a Gamma(m, Gamma) time (shape m, rate Gamma).  Sampled by Marsaglia and Tsang's
+ * method for shape a >= 1 ("A simple method for generating gamma variables",
+ * 2000): d = a - 1/3, c = 1/sqrt(9 d); draw a standard normal x and a uniform u;
+ * with v = (1 + c x)^3 > 0 accept d v if u < 1 - 0.0331 x^4 or
+ * ln u < x^2/2 + d (1 - v + ln v), else try again.  Attempt k of hop h (h counts the
+ * executed hops, this one included) reads the
+ * stream GAMMA | k << 8 at index h: x by Box-Muller from a 52-bit uniform and a
+ * 32-bit angle, u from the fourth word.  After 64 rejected attempts (probability
+ * below 1e-80) the mean m / Gamma is used.  Returns the increment.  */
+double or_gamma_dt(uint64_t seed, uint32_t sample_id, uint64_t hop, uint64_t m, double Gamma) {
+  const double d = (double)m - 1.0 / 3.0;
+  const double c = 1.0 / sqrt(9.0 * d);
+  for (uint32_t k = 0; k < 64; ++k) {
+    uint32_t ctr[4] = {(uint32_t)hop, (uint32_t)(hop >> 32), sample_id, (uint32_t)TAG_GAMMA | (k << 8)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    or_philox(ctr, key, w);
+    const double u1 = unit52(w[0], w[1]);
+    const double u2 = ((double)w[2] + 0.5) * 0x1p-32;
+    const double u = ((double)w[3] + 0.5) * 0x1p-32;
+    const double x = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    double v = 1.0 + c * x;
+    if (v <= 0.0) continue;
+    v = v * v * v;
+    const double x2 = x * x;
+    if (u < 1.0 - 0.0331 * (x2 * x2)) return d * v / Gamma;
+    if (log(u) < 0.5 * x2 + d * (1.0 - v + log(v))) return d * v / Gamma;
+  }
+  return (double)m / Gamma;
+}
+
 /* Clock: after each executed hop with m serial proposals since the previous
  * one, t advances by m/Gamma (deterministic increment used for the conductivity
- * figure) or by a Gaussian of mean m/Gamma and deviation sqrt(m)/Gamma (step 3c),
- * clamped at zero.  The Gaussian uses Box-Muller on stream CLOCK, index = hop.  */
+ * figure), by a Gaussian of mean m/Gamma and deviation sqrt(m)/Gamma (step 3c),
+ * clamped at zero, or by the exact Gamma(m, Gamma) time of the serial algorithm.
+ * The Gaussian uses Box-Muller on stream CLOCK, index = hop.  */
 static void advance_clock(or_state* st, uint64_t m) {
   if (st->p.clock_mode == 0) {
     st->t = (double)st->s_last / st->Gamma;
+    return;
+  }
+  if (st->p.clock_mode == 2) {
+    st->t = st->t + or_gamma_dt(st->p.seed, st->p.sample_id, st->hops, m, st->Gamma);
     return;
   }
   uint32_t w[4];

@@ -47,7 +47,8 @@ typedef struct or_params {
   double E;           /* field strength along +x */
   uint64_t seed;      /* Philox key (lo, hi) */
   uint32_t sample_id; /* Philox counter word 2 */
-  int32_t clock_mode; /* 0: dt = m/Gamma ; 1: Gaussian dt (mean m/Gamma, sd sqrt(m)/Gamma) */
+  int32_t clock_mode; /* 0: dt = m/Gamma ; 1: Gaussian dt (mean m/Gamma, sd sqrt(m)/Gamma) ;
+                         2: exact Gamma(m, Gamma) dt of the serial algorithm */
 } or_params;
 
 typedef struct or_scalars {
@@ -118,6 +119,10 @@ double or_energy(const or_state* st);
 double or_move(const or_state* st, int32_t i, int32_t v, double* dH);
 /* Exact acceptance probability of one proposal in the current configuration. */
 double or_acceptance(const or_state* st);
+
+/* Exact serial clock increment of hop `hop` after m proposals: a Gamma(m, Gamma) draw
+ * (Marsaglia-Tsang) from the GAMMA stream of (seed, sample_id). */
+double or_gamma_dt(uint64_t seed, uint32_t sample_id, uint64_t hop, uint64_t m, double Gamma);
 
 /* Planted mistakes for checking that the tests detect them (0 = none). */
 void or_set_mutation(int32_t m);
