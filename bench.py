@@ -45,16 +45,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(kernel: str):
     """HBM bytes per hop-kernel launch from the committed counter runs (FETCH_SIZE and
-    WRITE_SIZE scaled by a copy kernel of known size), or None when the kernel source has
-    changed since those counters were taken."""
+    WRITE_SIZE scaled by a copy kernel of known size), or None when they were taken on
+    another kernel instance or the kernel source has changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash() or not t.get("kernel", "").endswith(kernel):
         return None
     return t.get("bytes_per_launch")
 
@@ -91,7 +91,7 @@ def cpu_baseline(warm: int, hops: int, seed: int, cores: int) -> dict:
 
 
 def run_form(cg, torch, samples, precision, args, hops_per_step):
-    opts = cg.make_opts(precision=precision, M=args.M, block=args.block, K_refresh=args.K)
+    opts = cg.make_opts(precision=precision, M=args.M, block=args.block, K_refresh=args.K, clock_mode=args.clock)
     b = cg.Batch(samples, opts)
     n = len(samples)
     for _ in range(args.warmup):
@@ -173,6 +173,8 @@ def main() -> int:
     ap.add_argument("--M", type=int, default=1024)
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--K", type=int, default=4096)
+    ap.add_argument("--clock", type=int, default=0,
+                    help="clock mode: 0 deterministic m/Gamma (default), 1 Gaussian, 2 exact Gamma(m)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--cpu-hops", type=int, default=8192)
     ap.add_argument("--cpu-cores", type=int, default=0)
@@ -227,6 +229,7 @@ def main() -> int:
     per_launch_hops = r32["hops"] / max(r32["hop_launches"], 1)
     mean_launch_s = r32["hop_ms"] / max(r32["hop_launches"], 1) * 1e-3
     achieved = bytes_per_hop * per_launch_hops / mean_launch_s / 1e9
+    kernel = f"k_hops_fx<128, {1 if args.M <= 1024 else 2}, {0 if args.clock == 0 else 1}, 16>"
     out = {
         "metric": "accepted hops/s per GPU (L=128, T=0.02, batched) FP32+refresh vs FP64 PR",
         "value": value,
@@ -246,7 +249,7 @@ def main() -> int:
                                f"sample in steps of {args.hops_per_step}, FP32 with FP64 refresh every "
                                f"{args.K} hops",
                    "batch": args.batch, "L": 128, "M": args.M, "block": args.block,
-                   "K_refresh": args.K, "hops_per_step": args.hops_per_step},
+                   "K_refresh": args.K, "hops_per_step": args.hops_per_step, "clock_mode": args.clock},
         "proposals_per_s": r32["proposals"] / r32["seconds"],
         "evaluated_labels_per_s": r32["evaluated"] / r32["seconds"],
         "fp32_max_drift": r32["max_drift"],
@@ -254,8 +257,8 @@ def main() -> int:
         "window_hops_per_sample": r32["window_hops"],
         "fp32_window_hops_per_s": [round(v) for v in r32["windows"]],
         "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": f"k_hops_fx<128, {1 if args.M <= 1024 else 2}, 0, 16>", "bytes_per_hop": bytes_per_hop,
+                     "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(kernel),
+                     "kernel": kernel, "bytes_per_hop": bytes_per_hop,
                      "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
     }
     if r64 is not None:

@@ -51,6 +51,9 @@ extern "C" {
 
 #define CG_CLOCK_DET 0    /* dt = m / Gamma (deterministic increment)                    */
 #define CG_CLOCK_GAUSS 1  /* dt ~ Gaussian(m/Gamma, sqrt(m)/Gamma), clamped at 0 (step 3c) */
+#define CG_CLOCK_GAMMA 2  /* dt ~ Gamma(m, Gamma): the serial mixed algorithm's m Exp(Gamma)
+                             waiting times (section "Hopping conduction in the Coulomb
+                             glass"), drawn by Marsaglia-Tsang from stream GAMMA            */
 
 /* One independent sample (disorder realisation / temperature / size).
  * Requirements: 3 <= L <= 192, or L a power of two in [256, 2048]; 1 <= n_electrons < L*L;
@@ -81,7 +84,7 @@ typedef struct cg_run_opts {
                           exact-geometry kernel's 8-wave form (same hops and energies
                           bit for bit, 8-11% fewer hops/s at L = 128); CG_EINVAL otherwise */
   int32_t K_refresh;   /* FP32 form: hops between FP64 refreshes (>= 1); 0 = 4096       */
-  int32_t clock_mode;  /* CG_CLOCK_DET or CG_CLOCK_GAUSS                                 */
+  int32_t clock_mode;  /* CG_CLOCK_DET, CG_CLOCK_GAUSS or CG_CLOCK_GAMMA                 */
   int32_t log_hops;    /* per-sample capacity of the executed-hop log (0 = no log)       */
   int32_t phase_timers;/* 1: accumulate per-phase shader cycles into cg_stats            */
   int32_t use_graph;   /* 1: cg_run_hops captures its launch sequence once per (n_hops,
@@ -167,6 +170,19 @@ int cg_get_current(cg_ctx* ctx, int32_t sample, double* t, int64_t* P, double* s
  * entries; *count receives the number copied. */
 int cg_get_hop_log(cg_ctx* ctx, int32_t sample, uint64_t* labels, int32_t* from, int32_t* to,
                    int64_t cap, int64_t* count);
+
+/* Single-particle density of states (section "Results": the normalized histogram
+ * g(eps, T) = sum_k delta_{d eps}(eps - eps_k) of the local energies of Eq. 2) of samples
+ * first .. first + count - 1, in their current configurations: every site's energy (FP64,
+ * or the FP32 pair's FP64 sum) goes to bin floor((eps - e_lo) * nbins / (e_hi - e_lo))
+ * computed in FP64 (nbins / (e_hi - e_lo) evaluated first).  host_occupied[nbins] and
+ * host_empty[nbins] receive the counts of occupied and empty sites per bin,
+ * host_outside[2] the sites below e_lo and at or above e_hi.  Dividing by the number of
+ * sites and the bin width (e_hi - e_lo) / nbins normalizes.  1 <= nbins <= 4096,
+ * e_lo < e_hi finite, 1 <= count <= 65535 (CG_EINVAL otherwise).  Synchronises the
+ * context stream; the counts use a scratch region of the arena. */
+int cg_dos(cg_ctx* ctx, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+           uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside);
 
 /* Checkpoint of one sample (the state the paper's algorithm carries from hop to hop: the
  * occupation of Eq. 1, the local energies of Eq. 2, the clock, the next label and the

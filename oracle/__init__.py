@@ -87,6 +87,8 @@ def lib():
         L.or_acceptance.argtypes = [C.c_void_p]
         L.or_acceptance.restype = C.c_double
         L.or_set_mutation.argtypes = [C.c_int32]
+        L.or_naive_run.argtypes = [C.c_void_p, C.c_double]
+        L.or_naive_run.restype = C.c_int64
         L.or_gamma_dt.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_double]
         L.or_gamma_dt.restype = C.c_double
         _lib = L
@@ -203,6 +205,13 @@ class Oracle:
             raise ValueError("run() needs the energies: this oracle was created lazy")
         k = min(done, cap)
         return lab[:k].copy(), li[:k].copy(), lj[:k].copy()
+
+    def naive_run(self, t_end: float) -> int:
+        """Naive serial KMC until the clock reaches t_end; returns the hops executed."""
+        done = lib().or_naive_run(self._h, float(t_end))
+        if done < 0:
+            raise ValueError("naive_run() needs the energies: this oracle was created lazy")
+        return int(done)
 
     def site_eps(self, l: int) -> float:
         """eps_l of the current occupation, O(N), same summation order as the full recompute."""

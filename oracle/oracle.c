@@ -41,7 +41,7 @@ void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3, TAG_GAMMA = 4 };
+enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3, TAG_GAMMA = 4, TAG_NAIVE = 5 };
 
 static void stream(const or_state* st, uint64_t idx, uint32_t tag, uint32_t w[4]);
 
@@ -75,6 +75,7 @@ struct or_state {
   uint64_t s_last, s_scan, hops, theta_pass;
   int64_t P;
   double t, H0;
+  uint64_t naive_k; /* proposals made by the naive algorithm */
 };
 
 static void stream(const or_state* st, uint64_t idx, uint32_t tag, uint32_t w[4]) {
@@ -507,6 +508,48 @@ static void advance_clock(or_state* st, uint64_t m) {
   double dt = mean + sd * z;
   if (dt < 0.0) dt = 0.0;
   st->t = st->t + dt;
+}
+
+/* Naive serial KMC (section "Hopping conduction in the Coulomb glass"): a proposal
+ * picks i and j != i uniformly among the N sites and is accepted with probability
+ * tau_0 Gamma_ij = Gamma^T_ij Gamma^A_ij, Gamma^T_ij = exp(-2 r_ij / xi) for the hops
+ * the mixed algorithm's tower holds (minimum-image r_ij^2 <= rc^2), 0 otherwise, and
+ * Gamma^A_ij = theta_ij min(1, exp(-dH/T)); the clock is (proposals made) / (N (N - 1)),
+ * i.e. +1 per N (N - 1) proposals.  Proposal k reads stream NAIVE at index k: i from
+ * w0, j from w1 (uniform over the N - 1 other sites), the acceptance uniform from
+ * w2, w3.  Runs until the clock reaches t_end and returns the hops executed.  */
+int64_t or_naive_run(or_state* st, double t_end) {
+  if (st->lazy) return -1;
+  const int32_t L = st->p.L, N = st->N;
+  const double pairs = (double)N * (double)(N - 1);
+  int64_t done = 0;
+  while ((double)st->naive_k / pairs < t_end) {
+    uint32_t w[4];
+    stream(st, st->naive_k, TAG_NAIVE, w);
+    st->naive_k++;
+    const int32_t i = (int32_t)(((uint64_t)w[0] * (uint64_t)N) >> 32);
+    int32_t j = (int32_t)(((uint64_t)w[1] * (uint64_t)(N - 1)) >> 32);
+    if (j >= i) ++j;
+    if (!(st->n[i] == 1 && st->n[j] == 0)) continue;
+    int32_t dx = wrap(j % L - i % L, L), dy = wrap(j / L - i / L, L);
+    if (dx >= L - dx) dx -= L;
+    if (dy >= L - dy) dy -= L;
+    if (!((double)(dx * dx + dy * dy) <= st->p.rc * st->p.rc)) continue;
+    const double vij = or_invr(st, dx, dy);
+    const double dH = ((st->eps[j] - st->eps[i]) - vij) - st->p.E * (double)dx;
+    const double gA = dH <= 0.0 ? 1.0 : exp(-dH / st->p.T);
+    const double gT = exp(-2.0 * sqrt((double)(dx * dx + dy * dy)) / st->p.xi);
+    if (!(unit52(w[2], w[3]) < gT * gA)) continue;
+    st->n[i] = 0;
+    st->n[j] = 1;
+    st->P += dx;
+    st->H0 = st->H0 + ((st->eps[j] - st->eps[i]) - vij);
+    st->hops++;
+    update_eps(st, i, j);
+    ++done;
+  }
+  st->t = (double)st->naive_k / pairs;
+  return done;
 }
 
 int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,

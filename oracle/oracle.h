@@ -110,6 +110,13 @@ int or_set_occ(or_state* st, const uint8_t* n);
 int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
                uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap);
 
+/* Naive serial KMC on the current configuration (uniform pair proposals, acceptance
+ * exp(-2 r/xi) theta min(1, exp(-dH/T)) within the cutoff, clock +1 per N (N - 1)
+ * proposals, its own proposal counter and stream), until the clock reaches t_end.  For the
+ * equivalence check against the mixed algorithm; not on a lazy state (-1).  Returns the
+ * hops executed. */
+int64_t or_naive_run(or_state* st, double t_end);
+
 /* O(N^2) recomputation of the local energies from the current occupation. */
 void or_recompute_eps(const or_state* st, double* out);
 /* Field-free energy of the current occupation from Eq. 1, O(N^2). */

@@ -18,6 +18,7 @@
 #include "hop_fx.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
+#include "observables.hpp"
 
 using namespace cg;
 
@@ -249,7 +250,7 @@ struct Plan {
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
   uint64_t max_labels = 1ull << 32;
-  size_t states_off = 0, samples_off = 0, order_off = 0, scratch_off = 0, total = 0;
+  size_t states_off = 0, samples_off = 0, order_off = 0, scratch_off = 0, hist_off = 0, total = 0;
   std::vector<SampleLayout> sl;
   std::vector<int32_t> order;
 };
@@ -309,7 +310,8 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
   if (p.precision == CG_FP64) p.K = 0;
   p.clock = o->clock_mode;
-  if (p.clock != CG_CLOCK_DET && p.clock != CG_CLOCK_GAUSS) return set_err(CG_EINVAL, "clock_mode=%d", p.clock);
+  if (p.clock != CG_CLOCK_DET && p.clock != CG_CLOCK_GAUSS && p.clock != CG_CLOCK_GAMMA)
+    return set_err(CG_EINVAL, "clock_mode=%d", p.clock);
   if (o->log_hops < 0) return set_err(CG_EINVAL, "log_hops=%d", o->log_hops);
   p.log_cap = o->log_hops;
   p.max_labels = o->max_labels_per_call ? o->max_labels_per_call : (1ull << 32);
@@ -461,6 +463,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.samples_off = off; off = align_up(off + sizeof(DevSample) * (size_t)n);
   p.order_off = off;   off = align_up(off + sizeof(int32_t) * (size_t)n);
   p.scratch_off = off; off = align_up(off + 64);
+  p.hist_off = off;    off = align_up(off + (size_t)(2 * kDosMaxBins + 2) * 8);
   p.total = off;
   // launch order: largest lattices first (a one-workgroup-per-sample batch finishes
   // with its slowest sample)
@@ -508,7 +511,7 @@ BigFn pick_big_uc(int32_t L, int32_t* grid) {
 }
 
 BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t* grid) {
-  if (clock == CG_CLOCK_GAUSS) return U == 1 ? pick_big_uc<1, 1>(L, grid) : pick_big_uc<2, 1>(L, grid);
+  if (clock != CG_CLOCK_DET) return U == 1 ? pick_big_uc<1, 1>(L, grid) : pick_big_uc<2, 1>(L, grid);
   return U == 1 ? pick_big_uc<1, 0>(L, grid) : pick_big_uc<2, 0>(L, grid);
 }
 
@@ -526,7 +529,7 @@ HopFn pick_fx(int32_t U, int32_t NC, int32_t NW) {
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
               int32_t block) {
   if (layout == kRaw)
-    return clock == CG_CLOCK_GAUSS ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);
+    return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);
   if (db) return pick_db(U, NC, exact);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
@@ -1231,6 +1234,37 @@ int cg_get_hop_log(cg_ctx* c, int32_t b, uint64_t* labels, int32_t* from, int32_
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   *count = k;
+  return CG_OK;
+}
+
+int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+           uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside) {
+  if (!c) return set_err(CG_EINVAL, "null context");
+  const int32_t n = (int32_t)c->desc.size();
+  if (first < 0 || count < 1 || first + count > n)
+    return set_err(CG_EINVAL, "samples %d .. %d outside 0 .. %d", first, first + count - 1, n - 1);
+  if (nbins < 1 || nbins > kDosMaxBins) return set_err(CG_EINVAL, "nbins=%d must be in 1 .. %d", nbins, kDosMaxBins);
+  if (!(e_hi > e_lo) || !std::isfinite(e_lo) || !std::isfinite(e_hi))
+    return set_err(CG_EINVAL, "energy range [%g, %g)", e_lo, e_hi);
+  if (!host_occupied || !host_empty || !host_outside) return set_err(CG_EINVAL, "null output");
+  if (count > 65535) return set_err(CG_EINVAL, "count=%d exceeds 65535", count);
+  int32_t max_N = 0;
+  for (int32_t b = first; b < first + count; ++b) max_N = std::max(max_N, c->desc[b].L * c->desc[b].L);
+  unsigned long long* d_hist = (unsigned long long*)(c->arena + c->plan.hist_off);
+  const int slots = 2 * nbins + 2;
+  hipLaunchKernelGGL(k_fill_u64, dim3((slots + 255) / 256), dim3(256), 0, c->stream, d_hist, slots);
+  const double scale = (double)nbins / (e_hi - e_lo);
+  const int chunks = (max_N + kDosBlock * kDosSitesPerThread - 1) / (kDosBlock * kDosSitesPerThread);
+  hipLaunchKernelGGL(k_dos, dim3(chunks, count), dim3(kDosBlock), 0, c->stream, c->d_samples, first,
+                     c->plan.precision == CG_FP64 ? 0 : 1, e_lo, scale, nbins, d_hist);
+  HIPCHK(hipGetLastError());
+  std::vector<uint64_t> h((size_t)slots);
+  HIPCHK(hipMemcpyAsync(h.data(), d_hist, 8 * (size_t)slots, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memcpy(host_occupied, h.data(), 8 * (size_t)nbins);
+  std::memcpy(host_empty, h.data() + nbins, 8 * (size_t)nbins);
+  host_outside[0] = h[2 * (size_t)nbins];
+  host_outside[1] = h[2 * (size_t)nbins + 1];
   return CG_OK;
 }
 

@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
           S.log_to[logged] = hj;
         }
       }
-      if (CLOCK != 0) *tclock = *tclock + gauss_dt(hops, m, C.sid, C.k0, C.k1, Gamma);
+      if (CLOCK != 0) *tclock = *tclock + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
     }
     logged += logged < log_cap ? 1 : 0;
 

@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
         log_from[logged] = hi;
         log_to[logged] = hj;
       }
-      if (CLOCK != 0) sh->t = sh->t + gauss_dt(hops, m, C.sid, C.k0, C.k1, Gamma);
+      if (CLOCK != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
     }
     logged += logged < log_cap ? 1 : 0;
     // the owners of i and j move their occupation marks: site (x, y) is slot (y / NW) NC +

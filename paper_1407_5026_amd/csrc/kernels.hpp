@@ -48,7 +48,7 @@ __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c
   }
 }
 
-enum : uint32_t { kTagPropose = 0, kTagOcc = 1, kTagPhi = 2, kTagClock = 3 };
+enum : uint32_t { kTagPropose = 0, kTagOcc = 1, kTagPhi = 2, kTagClock = 3, kTagGamma = 4 };
 
 // (2k+1) 2^-53 with k the 52 bits hi:lo>>12 -- uniform in (0,1), exact in FP64.
 __device__ __forceinline__ double unit52(uint32_t hi, uint32_t lo) {
@@ -166,6 +166,40 @@ __device__ __noinline__ double gauss_dt(uint64_t h, uint64_t m, uint32_t sid, ui
   const double sd = sqrt((double)m) / Gamma;
   const double dt = mean + sd * z;
   return dt < 0.0 ? 0.0 : dt;
+}
+
+// Exact serial clock (clock mode 2): the m proposals up to an executed hop each add an
+// Exp(Gamma) waiting time in the serial mixed algorithm, so the hop adds a Gamma(m, Gamma)
+// time.  Marsaglia and Tsang's method for shape m >= 1 (2000): d = m - 1/3,
+// c = 1/sqrt(9 d); from a standard normal x (Box-Muller: 52-bit uniform, 32-bit angle) and a
+// 32-bit uniform u, with v = (1 + c x)^3 > 0, accept d v when u < 1 - 0.0331 x^4 or
+// ln u < x^2/2 + d (1 - v + ln v).  Attempt k of hop h draws Philox4x32-10 of
+// (h, sample, GAMMA | k << 8); after 64 rejections (probability < 1e-80) the mean m / Gamma.
+__device__ __noinline__ double gamma_dt(uint64_t h, uint64_t m, uint32_t sid, uint32_t k0, uint32_t k1,
+                                        double Gamma) {
+  const double d = (double)m - 1.0 / 3.0;
+  const double c = 1.0 / sqrt(9.0 * d);
+  for (uint32_t k = 0; k < 64; ++k) {
+    uint32_t c0 = (uint32_t)h, c1 = (uint32_t)(h >> 32), c2 = sid, c3 = kTagGamma | (k << 8);
+    philox10(c0, c1, c2, c3, k0, k1);
+    const double u1 = unit52(c0, c1);
+    const double u2 = ((double)c2 + 0.5) * 0x1p-32;
+    const double u = ((double)c3 + 0.5) * 0x1p-32;
+    const double x = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    double v = 1.0 + c * x;
+    if (v <= 0.0) continue;
+    v = v * v * v;
+    const double x2 = x * x;
+    if (u < 1.0 - 0.0331 * (x2 * x2)) return d * v / Gamma;
+    if (log(u) < 0.5 * x2 + d * (1.0 - v + log(v))) return d * v / Gamma;
+  }
+  return (double)m / Gamma;
+}
+
+// Clock increment of a stochastic clock mode: 1 Gaussian (step 3c), 2 exact Gamma(m).
+__device__ __forceinline__ double clock_dt(int mode, uint64_t h, uint64_t m, uint32_t sid, uint32_t k0,
+                                           uint32_t k1, double Gamma) {
+  return mode == 2 ? gamma_dt(h, m, sid, k0, k1, Gamma) : gauss_dt(h, m, sid, k0, k1, Gamma);
 }
 
 // Smallest label s with s / Gamma >= t_end (the deterministic clock is s_last / Gamma).
@@ -450,7 +484,7 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         S.log_from[logged] = h.i;
         S.log_to[logged] = h.j;
       }
-      if (ra.clock_mode != 0) sh->t = sh->t + gauss_dt(hops, m, sid, k0, k1, S.Gamma);
+      if (ra.clock_mode != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, sid, k0, k1, S.Gamma);
     }
     if (logged < S.log_cap) ++logged;
     CG_MARK(tc2)
@@ -822,7 +856,7 @@ __global__ void __launch_bounds__(1024) k_hops_db(const DevSample* __restrict__ 
         S.log_from[logged] = hi;
         S.log_to[logged] = hj;
       }
-      if (ra.clock_mode != 0) sh->t = sh->t + gauss_dt(hops, m, sid, k0, k1, S.Gamma);
+      if (ra.clock_mode != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, sid, k0, k1, S.Gamma);
     }
     if (logged < S.log_cap) ++logged;
     pend = true;

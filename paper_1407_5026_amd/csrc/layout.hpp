@@ -97,7 +97,7 @@ struct RunArgs {
   int32_t log2M;
   int32_t K;            // FP32 form: stop a sample when since_refresh reaches K (0: never)
   int32_t time_mode;    // 1: stop after the hop that brings t >= t_end
-  int32_t clock_mode;   // 0: t = s_last / Gamma ; 1: Gaussian increments
+  int32_t clock_mode;   // 0: t = s_last / Gamma ; 1: Gaussian increments ; 2: Gamma(m) increments
   int32_t timers;       // 1: accumulate per-phase shader cycles
   uint64_t max_labels;  // per-call label cap (stall guard)
 };

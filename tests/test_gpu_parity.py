@@ -188,6 +188,47 @@ def test_gaussian_clock():
     assert abs(t_gpu - t_or) <= 1e-9 * t_or, (t_gpu, t_or)
 
 
+@pytest.mark.parametrize("variant,L", [(0, 16), (3, 64), (4, 128)])
+def test_gamma_clock(variant, L):
+    """Exact serial clock (Gamma(m) increments): the hops are the oracle's and the clock
+    agrees to rounding (device and host log/cos/sqrt may differ in the last bit), in the
+    generic FP64 kernel (L=16), the exact-geometry FP32 kernel (L=64, clock only) and the
+    whole-GPU kernel (L=128, variant 4); run-to-time stops at the oracle's hop."""
+    cg = require_gpu()
+    if L == 16:
+        s, prec = serial_small(seed=13)[0], cg.CG_FP64
+    else:
+        s = Sample(L, L * L // 2, 1.0, 1.0, 8.0, 0.05, 0.01, 31, 0)
+        prec = cg.CG_FP32_REFRESH if variant == 3 else cg.CG_FP64
+    hops = 3000
+    b = _batch(cg, [s], precision=prec, log_hops=hops, clock_mode=cg.CG_CLOCK_GAMMA, variant=variant)
+    b.run_hops(hops)
+    o = oracle_of(s, clock_mode=2)
+    ol = o.run(hops)
+    if prec == cg.CG_FP64:
+        assert compare_logs(s, b.hop_log(0), ol) == hops
+        t_gpu, t_or = b.stats(0)["t"], o.scalars()["t"]
+        assert abs(t_gpu - t_or) <= 1e-12 * t_or, (t_gpu, t_or)
+        # run to a time: the stopping hop is the oracle's
+        t_end = t_or * 1.37
+        b.run_time(t_end)
+        o.run(0, t_end=t_end)
+        assert b.stats(0)["hops"] == o.scalars()["hops"] > hops
+    else:
+        # FP32 hops may leave the FP64 path at a near-tie; the clock of the hops both executed
+        # is the sum of the same increments
+        import oracle
+
+        gl = b.hop_log(0)[0].astype(np.int64)
+        m = np.diff(np.concatenate([[0], gl]))
+        G = o.tower()["Gamma"]
+        t = 0.0
+        for h, mm in enumerate(m.tolist(), start=1):
+            t = t + oracle.gamma_dt(s.seed, s.sample_id, h, mm, G)
+        assert abs(b.stats(0)["t"] - t) <= 1e-12 * t
+    say(f"Gamma clock variant {variant} L={L}: t = {b.stats(0)['t']:.6g}")
+
+
 def test_fp32_refresh_drift_and_energies():
     cg = require_gpu()
     s = Sample(64, 2048, 1.0, 1.0, 8.0, 0.05, 0.01, 2, 0)

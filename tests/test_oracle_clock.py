@@ -37,3 +37,35 @@ def test_run_with_the_gamma_clock_adds_the_increments():
     for h, mm in enumerate(m.tolist(), start=1):  # the clock streams index hops from 1
         t = t + oracle.gamma_dt(3, 1, h, mm, G)
     assert o.scalars()["t"] == t
+
+
+def _rates(o, run_to, t1, t2):
+    run_to(o, t1)
+    s0 = o.scalars()
+    run_to(o, t2)
+    s1 = o.scalars()
+    dt = s1["t"] - s0["t"]
+    return (s1["hops"] - s0["hops"]) / dt, (s1["P"] - s0["P"]) / dt
+
+
+def test_naive_kmc_and_the_mixed_algorithm_share_the_time_axis():
+    """The mixed algorithm with the exact Gamma(m) clock is equivalent to naive KMC (uniform
+    pair proposals, clock +1 per N(N-1) proposals): over the same stretch of simulated time
+    both execute the same mean number of hops and move the same mean dipole.  Paired by
+    disorder (each seed gives both chains the same phi and initial configuration; their
+    dynamics draw from different streams), 16 seeds, mean difference within 4 standard
+    errors; the comparison resolves a 10% error in the clock."""
+    kw = dict(L=8, n_e=32, W=1.0, xi=1.0, rc=2.5, T=0.25, E=0.1)
+    t1, t2 = 100.0, 1100.0
+    naive, mixed = [], []
+    for seed in range(1, 17):
+        naive.append(_rates(oracle.Oracle(seed=seed, **kw), lambda o, t: o.naive_run(t), t1, t2))
+        mixed.append(_rates(oracle.Oracle(seed=seed, clock_mode=2, **kw),
+                            lambda o, t: o.run(0, t_end=t, log_cap=0), t1, t2))
+    d = np.array(naive) - np.array(mixed)
+    se = d.std(axis=0, ddof=1) / np.sqrt(len(d))
+    for k, what in ((0, "hops per unit time"), (1, "dipole per unit time")):
+        assert abs(d[:, k].mean()) < 4 * se[k], (what, d[:, k].mean(), se[k])
+    rate = np.array(mixed)[:, 0].mean()
+    assert 0.1 * rate > 4 * se[0], (rate, se[0])
+    assert np.array(mixed)[:, 1].mean() > 0  # the field drives a current along +x
