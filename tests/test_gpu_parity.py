@@ -426,3 +426,56 @@ def test_checkpoint_restores_exactly(prec):
     with pytest.raises(cg.CgError):
         other.load(1, blob)  # other precision
     say(f"checkpoint precision={prec}: {len(blob)} bytes, 900 hops after the load identical")
+
+
+def test_degenerate_cases_hop_for_hop():
+    """The method's edge cases in one batch, FP64 against the oracle hop for hop: a single
+    electron, a single hole, no disorder and no field, the smallest cutoff (4 neighbours) and
+    the largest (rc just under L/2), the smallest lattice (L = 3), strong and weak
+    localization, a high temperature where almost every filtered proposal is accepted."""
+    cg = require_gpu()
+    samples = [Sample(12, 1, 1.0, 1.0, 3.0, 0.3, 0.01, 51, 0),
+               Sample(12, 143, 1.0, 1.0, 3.0, 0.3, 0.01, 51, 1),
+               Sample(16, 128, 0.0, 1.0, 6.0, 0.1, 0.0, 51, 2),
+               Sample(16, 128, 1.0, 1.0, 1.0, 0.1, 0.01, 51, 3),
+               Sample(16, 128, 1.0, 1.0, 7.9, 0.1, 0.01, 51, 4),
+               Sample(3, 4, 1.0, 1.0, 1.0, 0.2, 0.05, 51, 5),
+               Sample(20, 200, 1.0, 0.3, 4.0, 0.1, 0.01, 51, 6),
+               Sample(20, 200, 1.0, 3.0, 6.0, 0.1, 0.01, 51, 7),
+               Sample(16, 128, 1.0, 1.0, 6.0, 5.0, 0.5, 51, 8)]
+    hops = 2000
+    b = _batch(cg, samples, precision=cg.CG_FP64, log_hops=hops)
+    b.run_hops(hops)
+    for k, s in enumerate(samples):
+        o = oracle_of(s)
+        agree = compare_logs(s, b.hop_log(k), o.run(hops))
+        assert agree == hops, k
+        assert float(np.abs(b.energies(k) - o.eps()).max()) <= 1e-12
+        st, sc = b.stats(k), o.scalars()
+        assert st["P"] == sc["P"] and abs(st["t"] - sc["t"]) <= 1e-12 * sc["t"]
+        assert int(b.occupation(k).sum()) == s.n_e
+    say(f"{len(samples)} degenerate samples: {hops} hops each equal to the oracle")
+
+
+def test_label_cap_stall_then_resume():
+    """At a temperature where hops are very rare (T = 0.004: ~10^5 labels per hop after
+    300 hops) the label cap stops calls with CG_ESTALL; the state stays consistent, and
+    calling again continues the oracle's trajectory exactly (labels are counter-based, so
+    where a call stops does not matter)."""
+    cg = require_gpu()
+    s = Sample(16, 128, 1.0, 1.0, 6.0, 0.004, 0.0, 52, 0)
+    n = 400
+    b = _batch(cg, [s], precision=cg.CG_FP64, log_hops=n, max_labels_per_call=200_000)
+    stalls = 0
+    while b.stats(0)["hops"] < n:
+        try:
+            b.run_hops(n - b.stats(0)["hops"])
+        except cg.CgError as e:
+            assert e.code == cg.CG_ESTALL
+            stalls += 1
+            assert stalls < 10_000
+    assert stalls > 10
+    o = oracle_of(s)
+    assert compare_logs(s, b.hop_log(0), o.run(n)) == n
+    assert float(np.abs(b.energies(0) - o.eps()).max()) <= 1e-12
+    say(f"label cap: {stalls} stalled calls, {n} hops equal to the oracle")
