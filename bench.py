@@ -45,10 +45,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per hop-kernel launch from the committed counter runs (FETCH_SIZE and
-    WRITE_SIZE scaled by a copy kernel of known size), or None when they were taken on
-    another kernel instance or the kernel source has changed since."""
+def counter_record(kernel: str):
+    """The committed counter record of the hop kernel (HBM bytes per launch from FETCH_SIZE
+    and WRITE_SIZE scaled by a copy kernel of known size; VALU and LDS instructions per hop),
+    or None when it was taken on another kernel instance or the kernel source has changed
+    since."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -56,7 +57,12 @@ def measured_traffic(kernel: str):
         return None
     if t.get("kernel_hash") != kernel_hash() or not t.get("kernel", "").endswith(kernel):
         return None
-    return t.get("bytes_per_launch")
+    return t
+
+
+def measured_traffic(kernel: str):
+    t = counter_record(kernel)
+    return None if t is None else t.get("bytes_per_launch")
 
 
 def _cpu_worker(args):
@@ -261,6 +267,13 @@ def main() -> int:
                      "kernel": kernel, "bytes_per_hop": bytes_per_hop,
                      "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
     }
+    rec = counter_record(kernel)
+    if rec is not None and "valu_insts_per_hop" in rec:
+        # VALU issue fraction: wave instructions per hop (counter run, hops 8192..12288 of each
+        # sample) x this run's hops/s, against 256 CUs x 1.7 wave instructions per clock (the
+        # probe's FP32 rate) x 2.4 GHz
+        out["valu_frac"] = rec["valu_insts_per_hop"] * value / (256 * 1.7 * 2.4e9)
+        out["lds_insts_per_hop"] = rec["lds_insts_per_hop"]
     if r64 is not None:
         out["fp64_value"] = r64["hops"] / r64["seconds"]
         out["fp64_window_hops_per_s"] = [round(v) for v in r64["windows"]]
