@@ -20,15 +20,18 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC3 = os.path.join(_HERE, "oracle3d.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (the checker's build, not a use of it)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f)
+                                             for f in (_SRC, _SRC3, os.path.join(_HERE, "oracle.h")))
+    if force or stale:
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, _SRC3, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -89,6 +92,21 @@ def lib():
         L.or_set_mutation.argtypes = [C.c_int32]
         L.or_naive_run.argtypes = [C.c_void_p, C.c_double]
         L.or_naive_run.restype = C.c_int64
+        L.or3_create.argtypes = [P(_Params), P(C.c_void_p)]
+        L.or3_create.restype = C.c_int
+        L.or3_destroy.argtypes = [C.c_void_p]
+        L.or3_draw.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int32), P(C.c_double)]
+        L.or3_invr.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+        L.or3_invr.restype = C.c_double
+        L.or3_run.argtypes = [C.c_void_p, C.c_int64, P(C.c_uint64), P(C.c_int32), P(C.c_int32), C.c_int64]
+        L.or3_run.restype = C.c_int64
+        L.or3_energy.argtypes = [C.c_void_p]
+        L.or3_energy.restype = C.c_double
+        L.or3_get.argtypes = [C.c_void_p, P(C.c_uint8), P(C.c_double), P(C.c_double)]
+        L.or3_scalars.argtypes = [C.c_void_p, P(_Scalars)]
+        L.or3_tower.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_uint64), P(C.c_int32),
+                                P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+        L.or3_set_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
         L.or_gamma_dt.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_double]
         L.or_gamma_dt.restype = C.c_double
         _lib = L
@@ -232,3 +250,75 @@ class Oracle:
 
     def acceptance(self) -> float:
         return lib().or_acceptance(self._h)
+
+
+class Oracle3D:
+    """Serial FP64 chain on the simple cubic lattice (L^3 sites), deterministic clock."""
+
+    def __init__(self, L, n_e, W=1.0, xi=1.0, rc=2.0, T=0.1, E=0.0, seed=1, sample_id=0):
+        self.params = dict(L=L, n_e=n_e, W=W, xi=xi, rc=rc, T=T, E=E, seed=seed, sample_id=sample_id)
+        p = _Params(L, n_e, W, xi, rc, T, E, seed, sample_id, 0)
+        h = C.c_void_p()
+        rc_ = lib().or3_create(C.byref(p), C.byref(h))
+        if rc_ != 0:
+            raise ValueError(f"or3_create failed ({rc_}) for {self.params}")
+        self._h = h
+        self.N = L * L * L
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().or3_destroy(self._h)
+            self._h = None
+
+    def tower(self) -> dict:
+        no, nv = C.c_int32(), C.c_int32()
+        lib().or3_tower(self._h, C.byref(no), C.byref(nv), None, None, None, None, None, None)
+        thr = np.zeros(no.value, np.uint64)
+        first = np.zeros(no.value, np.int32)
+        size = np.zeros(no.value, np.int32)
+        vx, vy, vz = (np.zeros(nv.value, np.int32) for _ in range(3))
+        lib().or3_tower(self._h, C.byref(no), C.byref(nv), _ptr(thr, C.c_uint64), _ptr(first, C.c_int32),
+                        _ptr(size, C.c_int32), _ptr(vx, C.c_int32), _ptr(vy, C.c_int32), _ptr(vz, C.c_int32))
+        return dict(thr=thr, first=first, size=size, dx=vx, dy=vy, dz=vz, Gamma=self.scalars()["Gamma"])
+
+    def draw(self, s: int):
+        i, v, u = C.c_int32(), C.c_int32(), C.c_double()
+        lib().or3_draw(self._h, s, C.byref(i), C.byref(v), C.byref(u))
+        return i.value, v.value, u.value
+
+    def invr(self, dx: int, dy: int, dz: int) -> float:
+        return lib().or3_invr(self._h, dx, dy, dz)
+
+    def occ(self) -> np.ndarray:
+        a = np.zeros(self.N, np.uint8)
+        lib().or3_get(self._h, _ptr(a, C.c_uint8), None, None)
+        return a
+
+    def eps(self) -> np.ndarray:
+        a = np.zeros(self.N, np.float64)
+        lib().or3_get(self._h, None, _ptr(a, C.c_double), None)
+        return a
+
+    def phi(self) -> np.ndarray:
+        a = np.zeros(self.N, np.float64)
+        lib().or3_get(self._h, None, None, _ptr(a, C.c_double))
+        return a
+
+    def scalars(self) -> dict:
+        s = _Scalars()
+        lib().or3_scalars(self._h, C.byref(s))
+        return {k: getattr(s, k) for k, _ in _Scalars._fields_}
+
+    def energy(self) -> float:
+        return lib().or3_energy(self._h)
+
+    def set_occ(self, n) -> None:
+        a = np.ascontiguousarray(n, dtype=np.uint8)
+        lib().or3_set_occ(self._h, _ptr(a, C.c_uint8))
+
+    def run(self, n_hops: int):
+        lab = np.zeros(max(n_hops, 1), np.uint64)
+        li = np.zeros(max(n_hops, 1), np.int32)
+        lj = np.zeros(max(n_hops, 1), np.int32)
+        k = lib().or3_run(self._h, n_hops, _ptr(lab, C.c_uint64), _ptr(li, C.c_int32), _ptr(lj, C.c_int32), n_hops)
+        return lab[:k].copy(), li[:k].copy(), lj[:k].copy()

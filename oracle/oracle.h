@@ -131,6 +131,23 @@ double or_acceptance(const or_state* st);
  * (Marsaglia-Tsang) from the GAMMA stream of (seed, sample_id). */
 double or_gamma_dt(uint64_t seed, uint32_t sample_id, uint64_t hop, uint64_t m, double Gamma);
 
+/* ---- simple cubic lattice (oracle3d.c): L^3 sites, the same parameters (clock_mode 0
+ * only), hop vectors in orbits of the cube's 48 symmetries, member mulhi(w3, size),
+ * acceptance uniform (w2 + 1/2) 2^-32. ---- */
+typedef struct or3_state or3_state;
+int or3_create(const or_params* p, or3_state** out);
+void or3_destroy(or3_state* st);
+void or3_draw(const or3_state* st, uint64_t s, int32_t* i, int32_t* v, double* u);
+double or3_invr(const or3_state* st, int32_t dx, int32_t dy, int32_t dz);
+int64_t or3_run(or3_state* st, int64_t n_hops, uint64_t* log_label, int32_t* log_i, int32_t* log_j,
+                int64_t log_cap);
+double or3_energy(const or3_state* st);
+void or3_get(const or3_state* st, uint8_t* n, double* eps, double* phi);
+void or3_scalars(const or3_state* st, or_scalars* out);
+void or3_tower(const or3_state* st, int32_t* n_orb, int32_t* n_vec, uint64_t* thr, int32_t* first,
+               int32_t* size, int32_t* vx, int32_t* vy, int32_t* vz);
+void or3_set_occ(or3_state* st, const uint8_t* n);
+
 /* Planted mistakes for checking that the tests detect them (0 = none). */
 void or_set_mutation(int32_t m);
 
