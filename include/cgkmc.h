@@ -71,7 +71,9 @@ typedef struct cg_sample_desc {
   double E;
   uint64_t seed;
   uint32_t sample_id;
-  uint32_t reserved; /* set to 0 */
+  int32_t dim;       /* lattice: 0 or 2 = square (L^2 sites), 3 = simple cubic (L^3 sites;
+                        FP64 form, deterministic clock, 3 <= L <= 24, every sample of the
+                        batch cubic); CG_EINVAL otherwise */
 } cg_sample_desc;
 
 typedef struct cg_run_opts {

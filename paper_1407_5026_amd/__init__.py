@@ -40,7 +40,7 @@ EXPORTS = (
 class cg_sample_desc(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_electrons", C.c_int32), ("W", C.c_double), ("xi", C.c_double),
                 ("rc", C.c_double), ("T", C.c_double), ("E", C.c_double), ("seed", C.c_uint64),
-                ("sample_id", C.c_uint32), ("reserved", C.c_uint32)]
+                ("sample_id", C.c_uint32), ("dim", C.c_int32)]
 
 
 class cg_run_opts(C.Structure):
@@ -123,7 +123,7 @@ def _descs(samples):
         d = s if isinstance(s, dict) else s.as_dict()
         arr[k] = cg_sample_desc(int(d["L"]), int(d.get("n_e", d.get("n_electrons"))), float(d["W"]),
                                 float(d["xi"]), float(d["rc"]), float(d["T"]), float(d["E"]),
-                                int(d["seed"]), int(d["sample_id"]), 0)
+                                int(d["seed"]), int(d["sample_id"]), int(d.get("dim", 2)))
     return arr
 
 
@@ -179,7 +179,7 @@ class Batch:
             stream = (torch.cuda.Stream(self.arena.device) if self.opts.use_graph
                       else torch.cuda.current_stream(self.arena.device))
         self.stream = stream
-        self.N = [int(d.L) * int(d.L) for d in self._descs]
+        self.N = [int(d.L) ** (3 if d.dim == 3 else 2) for d in self._descs]
         h = C.c_void_p()
         _check(lib.cg_create(C.byref(h), self._descs, self.n, C.byref(self.opts),
                              C.c_void_p(self._arena_ptr), nbytes, C.c_void_p(self.stream.cuda_stream)))

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +15,7 @@
 #include <vector>
 
 #include "cgkmc.h"
+#include "hop3d.hpp"
 #include "hop_big.hpp"
 #include "hop_fx.hpp"
 #include "kernels.hpp"
@@ -267,8 +269,109 @@ int max_lds_bytes(int32_t* out) {
 
 bool big_eligible(int32_t L) { return L >= 128 && L <= 2048 && (L & (L - 1)) == 0; }
 
+bool is_cube(const cg_sample_desc& d) { return d.dim == 3; }
+int32_t sites_of(const cg_sample_desc& d) { return is_cube(d) ? d.L * d.L * d.L : d.L * d.L; }
+
+// Proposal law on the simple cubic lattice: displacements 0 < |d|^2 <= rc^2, weight
+// exp(-2|d|/xi), in orbits of the cube's 48 signed permutations ordered by (|d|^2, largest
+// coordinate, middle coordinate); members in ascending (dz, dy, dx); orbit o is the first
+// with w1 < thr[o], thr[o] = floor(2^32 * cumulative weight / total); member
+// mulhi(w3, size).  orb[o] = first | size << 16, vec = packed (dx, dy, dz).  Table: 1/r by
+// folded (|dz|, |dy|, |dx|), 0 at the origin.
+struct Rep3 {
+  int32_t a, b, c, r2;
+};
+
+void cube_reps(double rc, std::vector<Rep3>& reps) {
+  reps.clear();
+  const int32_t amax = (int32_t)std::floor(rc) + 1;
+  for (int32_t a = 1; a <= amax; ++a)
+    for (int32_t b = 0; b <= a; ++b)
+      for (int32_t c = 0; c <= b; ++c)
+        if ((double)(a * a + b * b + c * c) <= rc * rc) reps.push_back({a, b, c, a * a + b * b + c * c});
+  std::sort(reps.begin(), reps.end(), [](const Rep3& p, const Rep3& q) {
+    if (p.r2 != q.r2) return p.r2 < q.r2;
+    if (p.a != q.a) return p.a < q.a;
+    return p.b < q.b;
+  });
+}
+
+int32_t count_vectors3(double rc) {
+  int32_t n = 0;
+  const int32_t k = (int32_t)std::floor(rc) + 1;
+  for (int32_t dz = -k; dz <= k; ++dz)
+    for (int32_t dy = -k; dy <= k; ++dy)
+      for (int32_t dx = -k; dx <= k; ++dx)
+        if ((dx || dy || dz) && (double)(dx * dx + dy * dy + dz * dz) <= rc * rc) ++n;
+  return n;
+}
+
+int build_tables3(const cg_sample_desc& d, HostTables& t) {
+  const int32_t L = d.L, N = L * L * L, H = L / 2, H1 = H + 1;
+  std::vector<Rep3> reps;
+  cube_reps(d.rc, reps);
+  const int32_t n_orb = (int32_t)reps.size();
+  if (n_orb < 1) return set_err(CG_EINVAL, "rc=%g gives no hop vector", d.rc);
+  t.n_orb = n_orb;
+  t.thr.assign(n_orb, 0u);
+  t.orb.assign(n_orb, 0u);
+  t.vec.clear();
+  std::vector<double> cum(n_orb);
+  double acc = 0.0;
+  for (int32_t o = 0; o < n_orb; ++o) {
+    const int32_t abc[3] = {reps[o].a, reps[o].b, reps[o].c};
+    std::vector<std::array<int32_t, 3>> m;  // (dz, dy, dx)
+    const int32_t perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (auto& pm : perm)
+      for (int32_t sg = 0; sg < 8; ++sg) {
+        const int32_t dx = abc[pm[0]] * ((sg & 1) ? -1 : 1), dy = abc[pm[1]] * ((sg & 2) ? -1 : 1),
+                      dz = abc[pm[2]] * ((sg & 4) ? -1 : 1);
+        const std::array<int32_t, 3> v = {dz, dy, dx};
+        if (std::find(m.begin(), m.end(), v) == m.end()) m.push_back(v);
+      }
+    std::sort(m.begin(), m.end());
+    t.orb[o] = (uint32_t)t.vec.size() | ((uint32_t)m.size() << 16);
+    for (auto& v : m) t.vec.push_back((int32_t)pack3(v[2], v[1], v[0]));
+    acc = acc + (double)m.size() * std::exp(-2.0 * std::sqrt((double)reps[o].r2) / d.xi);
+    cum[o] = acc;
+  }
+  t.n_vec = (int32_t)t.vec.size();
+  for (int32_t o = 0; o + 1 < n_orb; ++o) {
+    const double c = std::floor(std::ldexp(cum[o] / acc, 32));
+    if (!(c < 4294967296.0))
+      return set_err(CG_EINVAL, "rc=%g: orbit weights beyond %d are below the 2^-32 resolution", d.rc, o);
+    t.thr[o] = (uint32_t)(uint64_t)c;
+  }
+  t.thr[n_orb - 1] = 0xffffffffu;  // never compared: the last orbit takes the rest
+  t.wsum = acc;
+  t.Gamma = (double)N * acc;
+  t.H = H;
+  t.tab64.assign((size_t)H1 * H1 * H1, 0.0);
+  for (int32_t c = 0; c < H1; ++c)
+    for (int32_t b = 0; b < H1; ++b)
+      for (int32_t a = 0; a < H1; ++a) {
+        const int32_t r2 = a * a + b * b + c * c;
+        t.tab64[((size_t)c * H1 + b) * H1 + a] = r2 == 0 ? 0.0 : 1.0 / std::sqrt((double)r2);
+      }
+  return CG_OK;
+}
+
 int validate(const cg_sample_desc& d, int32_t b) {
   const int32_t L = d.L;
+  if (d.dim != 0 && d.dim != 2 && d.dim != 3) return set_err(CG_EINVAL, "sample %d: dim=%d", b, d.dim);
+  if (is_cube(d)) {
+    if (L < 3 || L > kCubeMaxL) return set_err(CG_EINVAL, "sample %d: cubic L=%d outside [3, %d]", b, L, kCubeMaxL);
+    const int32_t N = L * L * L;
+    if (d.n_electrons < 1 || d.n_electrons >= N)
+      return set_err(CG_EINVAL, "sample %d: n_electrons=%d outside [1, N-1]", b, d.n_electrons);
+    if (!(d.W >= 0.0) || !std::isfinite(d.W)) return set_err(CG_EINVAL, "sample %d: W=%g", b, d.W);
+    if (!(d.xi > 0.0) || !std::isfinite(d.xi)) return set_err(CG_EINVAL, "sample %d: xi=%g", b, d.xi);
+    if (!(d.rc >= 1.0) || !(2.0 * d.rc < (double)L))
+      return set_err(CG_EINVAL, "sample %d: rc=%g must satisfy 1 <= rc < L/2 = %g", b, d.rc, 0.5 * L);
+    if (!(d.T > 0.0) || !std::isfinite(d.T)) return set_err(CG_EINVAL, "sample %d: T=%g must be > 0", b, d.T);
+    if (!std::isfinite(d.E)) return set_err(CG_EINVAL, "sample %d: E=%g", b, d.E);
+    return CG_OK;
+  }
   if (L < 3 || (L > 192 && !big_eligible(L)))
     return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 192] and not a power of two in [256, 2048]", b, L);
   const int32_t N = L * L;
@@ -280,6 +383,83 @@ int validate(const cg_sample_desc& d, int32_t b) {
     return set_err(CG_EINVAL, "sample %d: rc=%g must satisfy 1 <= rc < L/2 = %g", b, d.rc, 0.5 * L);
   if (!(d.T > 0.0) || !std::isfinite(d.T)) return set_err(CG_EINVAL, "sample %d: T=%g must be > 0", b, d.T);
   if (!std::isfinite(d.E)) return set_err(CG_EINVAL, "sample %d: E=%g", b, d.E);
+  return CG_OK;
+}
+
+// Offsets of the batch-wide blocks after the samples' regions, and the launch order.
+void plan_tail(const cg_sample_desc* s, int32_t n, Plan& p, size_t off) {
+  p.samples_off = off; off = align_up(off + sizeof(DevSample) * (size_t)n);
+  p.order_off = off;   off = align_up(off + sizeof(int32_t) * (size_t)n);
+  p.scratch_off = off; off = align_up(off + 64);
+  p.hist_off = off;    off = align_up(off + (size_t)(2 * kDosMaxBins + 2) * 8);
+  p.total = off;
+  // launch order: largest lattices first (a one-workgroup-per-sample batch finishes
+  // with its slowest sample)
+  p.order.resize(n);
+  for (int32_t b = 0; b < n; ++b) p.order[b] = b;
+  std::stable_sort(p.order.begin(), p.order.end(), [&](int32_t a, int32_t c) { return s[a].L > s[c].L; });
+}
+
+// Batch of simple cubic samples: FP64 energies and tables in LDS (k_hops3), initial energies
+// by k_eps3, no refresh.
+int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
+  for (int32_t b = 0; b < n; ++b) {
+    if (!is_cube(s[b])) return set_err(CG_EINVAL, "sample %d: a batch is either all square or all cubic", b);
+    int rc = validate(s[b], b);
+    if (rc != CG_OK) return rc;
+  }
+  if (p.precision != CG_FP64) return set_err(CG_EINVAL, "cubic lattices run the FP64 form");
+  if (p.clock != CG_CLOCK_DET) return set_err(CG_EINVAL, "cubic lattices use the deterministic clock");
+  if (p.variant != 0 || p.block != 1024) return set_err(CG_EINVAL, "cubic lattices: variant 0, block 1024");
+  p.layout = kCube;
+  p.big = false;
+  p.U = 1;
+  p.NC = 1;
+  int32_t need = 0, need_exact = 0, max_N = 0;
+  for (int32_t b = 0; b < n; ++b) {
+    std::vector<Rep3> reps;
+    cube_reps(s[b].rc, reps);
+    const int32_t L = s[b].L, N = L * L * L, H1 = L / 2 + 1;
+    need = std::max(need, cube_lds(L, (int32_t)reps.size(), count_vectors3(s[b].rc)).total);
+    need_exact = std::max(need_exact, align16(((N + 31) / 32) * 4) + H1 * H1 * H1 * 8);
+    max_N = std::max(max_N, N);
+  }
+  if (need > lds_cap) return set_err(CG_ENOSPC, "cubic samples need %d bytes of LDS (%d available)", need, lds_cap);
+  if (need_exact + 2 * kInitBlock * 8 > lds_cap)
+    return set_err(CG_ENOSPC, "cubic energy kernel needs %d bytes of LDS", need_exact);
+  p.lds_hop = need;
+  p.lds_exact = need_exact;
+  p.max_N = max_N;
+  size_t off = 0;
+  p.sl.resize(n);
+  p.states_off = off;
+  off = align_up(off + sizeof(SampleState) * (size_t)n);
+  for (int32_t b = 0; b < n; ++b) {
+    std::vector<Rep3> reps;
+    cube_reps(s[b].rc, reps);
+    const int32_t L = s[b].L, N = L * L * L, NW = (N + 31) / 32, H1 = L / 2 + 1;
+    const int32_t n_orb = (int32_t)reps.size(), n_vec = count_vectors3(s[b].rc);
+    const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
+    SampleLayout& q = p.sl[b];
+    q.dft = 0;
+    q.tab64 = off;     off = align_up(off + (size_t)H1 * H1 * H1 * 8);
+    q.tabk = off;
+    q.thr = off;       off = align_up(off + (size_t)n_orb * 4);
+    q.orb = off;       off = align_up(off + (size_t)n_orb * 4);
+    q.vec = off;       off = align_up(off + (size_t)n_vec * 4);
+    q.guide = q.vec8 = q.guide16 = q.tdo64 = q.dft_tw = q.dft_T = off;
+    q.static_end = off;
+    q.eps = off;       off = align_up(off + (size_t)N * 8);
+    q.phi = off;       off = align_up(off + (size_t)N * 8);
+    q.occ = off;       off = align_up(off + (size_t)NW * 4);
+    q.part = off;      off = align_up(off + (size_t)2 * nblk * 8);
+    q.log_label = off; off = align_up(off + (size_t)p.log_cap * 8);
+    q.log_from = off;  off = align_up(off + (size_t)p.log_cap * 4);
+    q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
+    q.mirror = q.sel = off;
+    q.end = off;
+  }
+  plan_tail(s, n, p, off);
   return CG_OK;
 }
 
@@ -322,6 +502,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     int rc = max_lds_bytes(&lds_cap);
     if (rc != CG_OK) return rc;
   }
+  if (is_cube(s[0])) return plan_cube(s, n, p, lds_cap);
   // table layout: full (|dy|,|dx|) table if every sample fits, else the triangle
   bool full_fits = true, tri_fits = true, db_fits = true;
   int32_t need_db = 0;
@@ -460,17 +641,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.NC = max_L <= 64 ? 1 : (max_L <= 128 ? 2 : 3);
   p.exact = true;
   for (int32_t b = 0; b < n; ++b) p.exact = p.exact && s[b].L == 64 * p.NC;
-  p.samples_off = off; off = align_up(off + sizeof(DevSample) * (size_t)n);
-  p.order_off = off;   off = align_up(off + sizeof(int32_t) * (size_t)n);
-  p.scratch_off = off; off = align_up(off + 64);
-  p.hist_off = off;    off = align_up(off + (size_t)(2 * kDosMaxBins + 2) * 8);
-  p.total = off;
-  // launch order: largest lattices first (a one-workgroup-per-sample batch finishes
-  // with its slowest sample)
-  p.order.resize(n);
-  for (int32_t b = 0; b < n; ++b) p.order[b] = b;
-  std::stable_sort(p.order.begin(), p.order.end(),
-                   [&](int32_t a, int32_t c) { return s[a].L > s[c].L; });
+  plan_tail(s, n, p, off);
   return CG_OK;
 }
 
@@ -528,6 +699,7 @@ HopFn pick_fx(int32_t U, int32_t NC, int32_t NW) {
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
               int32_t block) {
+  if (layout == kCube) return k_hops3;
   if (layout == kRaw)
     return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);
   if (db) return pick_db(U, NC, exact);
@@ -682,7 +854,13 @@ int launch_exact(cg_ctx* c, int refresh) {
       HIPCHK(hipGetLastError());
     }
   }
-  if (p.big) {
+  if (p.layout == kCube) {
+    // FP64 form: the initial energies, or a forced recompute (cg_refresh)
+    hipLaunchKernelGGL(k_eps3, grid, dim3(kInitBlock), p.lds_exact, c->stream, c->d_samples, refresh);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(n), dim3(64), 0, c->stream, c->d_samples, refresh, p.K);
+    HIPCHK(hipGetLastError());
+  } else if (p.big) {
     for (int32_t b = 0; b < n; ++b) {
       const int32_t nb = (c->desc[b].L * c->desc[b].L + kInitBlock - 1) / kInitBlock;
       hipLaunchKernelGGL(k_eps_big, dim3(nb), dim3(kInitBlock), 0, c->stream, c->d_samples + b, refresh);
@@ -807,9 +985,9 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     const cg_sample_desc& d = samples[b];
     const SampleLayout& q = p.sl[b];
     HostTables t;
-    rc = build_tables(d, p.layout, p.precision, p.block / 64, t);
+    rc = p.layout == kCube ? build_tables3(d, t) : build_tables(d, p.layout, p.precision, p.block / 64, t);
     if (rc != CG_OK) return fail(rc);
-    const int32_t L = d.L, N = L * L;
+    const int32_t L = d.L, N = sites_of(d);
     const uint32_t magic = (uint32_t)((((uint64_t)1 << 32) + (uint64_t)L - 1) / (uint64_t)L);
     for (int32_t i = 0; i < N; ++i)
       if ((int32_t)(((uint64_t)i * magic) >> 32) != i / L)
@@ -818,7 +996,9 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     sb.assign(q.static_end - q.tab64, 0);
     uint8_t* base = sb.data() - q.tab64;
     std::memcpy(base + q.tab64, t.tab64.data(), t.tab64.size() * 8);
-    if (p.precision == CG_FP64)
+    if (p.layout == kCube)
+      ;  // no kernel table beyond the FP64 one
+    else if (p.precision == CG_FP64)
       std::memcpy(base + q.tabk, t.tabk64.data(), t.tabk64.size() * 8);
     else
       std::memcpy(base + q.tabk, t.tabk32.data(), t.tabk32.size() * 4);
@@ -843,7 +1023,10 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.NW = (N + 31) / 32;
     s.n_orb = t.n_orb;
     s.n_vec = t.n_vec;
-    s.ntab = p.layout == kTri ? tri_entries(t.H) : p.layout == kRaw ? fx_tab_entries(L, p.block / 64) : full_entries(t.H);
+    s.ntab = p.layout == kTri    ? tri_entries(t.H)
+             : p.layout == kRaw  ? fx_tab_entries(L, p.block / 64)
+             : p.layout == kCube ? (t.H + 1) * (t.H + 1) * (t.H + 1)
+                                 : full_entries(t.H);
     s.nblk = (N + kInitBlock - 1) / kInitBlock;
     s.log_cap = p.log_cap;
     s.layout = p.layout;
@@ -907,7 +1090,9 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
 
   if (!p.big)
     HIPCHK_C(hipFuncSetAttribute((const void*)c->hop, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop));
-  if (p.precision == CG_FP64) {
+  if (p.layout == kCube) {
+    HIPCHK_C(hipFuncSetAttribute((const void*)k_eps3, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_exact));
+  } else if (p.precision == CG_FP64) {
     HIPCHK_C(hipFuncSetAttribute((const void*)k_eps_exact<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  p.lds_exact));
   } else {
@@ -1249,7 +1434,7 @@ int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, in
   if (!host_occupied || !host_empty || !host_outside) return set_err(CG_EINVAL, "null output");
   if (count > 65535) return set_err(CG_EINVAL, "count=%d exceeds 65535", count);
   int32_t max_N = 0;
-  for (int32_t b = first; b < first + count; ++b) max_N = std::max(max_N, c->desc[b].L * c->desc[b].L);
+  for (int32_t b = first; b < first + count; ++b) max_N = std::max(max_N, c->dev[b].N);
   unsigned long long* d_hist = (unsigned long long*)(c->arena + c->plan.hist_off);
   const int slots = 2 * nbins + 2;
   hipLaunchKernelGGL(k_fill_u64, dim3((slots + 255) / 256), dim3(256), 0, c->stream, d_hist, slots);
@@ -1272,7 +1457,7 @@ int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, in
 struct SaveHeader {
   char magic[8];  // "CGKMCSV1"
   uint32_t version, state_bytes;
-  int32_t precision, L, n_e, pad_;
+  int32_t precision, L, n_e, dim;
   double W, xi, rc, T, E;
   uint64_t seed;
   uint32_t sample_id, occ_words;
@@ -1301,6 +1486,7 @@ int cg_save(cg_ctx* c, int32_t b, void* host_blob, size_t* bytes) {
   h.state_bytes = (uint32_t)sizeof(SampleState);
   h.precision = c->plan.precision;
   h.L = d.L;
+  h.dim = d.dim;
   h.n_e = d.n_electrons;
   h.W = d.W;
   h.xi = d.xi;
@@ -1340,7 +1526,7 @@ int cg_load(cg_ctx* c, int32_t b, const void* host_blob, size_t bytes) {
     return set_err(CG_EINVAL, "checkpoint of %zu bytes does not match sample %d (%zu bytes)", bytes, b, need);
   if (h.precision != c->plan.precision)
     return set_err(CG_EINVAL, "checkpoint precision %d, context precision %d", h.precision, c->plan.precision);
-  if (h.L != d.L || h.n_e != d.n_electrons || h.W != d.W || h.xi != d.xi || h.rc != d.rc || h.seed != d.seed ||
+  if (h.L != d.L || h.dim != d.dim || h.n_e != d.n_electrons || h.W != d.W || h.xi != d.xi || h.rc != d.rc || h.seed != d.seed ||
       h.sample_id != d.sample_id)
     return set_err(CG_EINVAL, "checkpoint is of another sample (L, n_e, W, xi, rc, seed or sample id differ)");
   SampleState st;

@@ -23,7 +23,7 @@ def dos(batch, first: int, count: int, e_lo: float, e_hi: float, nbins: int):
     """GPU counts and the normalized g(eps) of samples first .. first + count - 1:
     (bin centres, g_total, g_occupied, g_empty, below, above)."""
     occ, emp, below, above = batch.dos(first, count, e_lo, e_hi, nbins)
-    n_sites = sum(batch.samples[b].L ** 2 for b in range(first, first + count))
+    n_sites = sum(batch.N[b] for b in range(first, first + count))
     width = (e_hi - e_lo) / nbins
     centres = e_lo + width * (np.arange(nbins) + 0.5)
     norm = 1.0 / (n_sites * width)

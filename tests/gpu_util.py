@@ -27,6 +27,9 @@ def require_gpu():
 
 def oracle_of(s, clock_mode=0):
     d = s if isinstance(s, dict) else s.as_dict()
+    if d.get("dim", 2) == 3:
+        return oracle.Oracle3D(L=d["L"], n_e=d["n_e"], W=d["W"], xi=d["xi"], rc=d["rc"], T=d["T"], E=d["E"],
+                               seed=d["seed"], sample_id=d["sample_id"])
     return oracle.Oracle(L=d["L"], n_e=d["n_e"], W=d["W"], xi=d["xi"], rc=d["rc"], T=d["T"], E=d["E"],
                          seed=d["seed"], sample_id=d["sample_id"], clock_mode=clock_mode)
 

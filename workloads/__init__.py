@@ -26,6 +26,7 @@ class Sample:
     E: float
     seed: int
     sample_id: int
+    dim: int = 2  # 2: square lattice (L^2 sites), 3: simple cubic (L^3 sites)
 
     def as_dict(self):
         return asdict(self)
