@@ -166,6 +166,40 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int) -> dict:
             "paper_gpu_ms_per_hop_T005": {"64": 0.10, "2048": 1.04}.get(str(L))}
 
 
+def cubic(cg, torch, L: int, batch: int, hops: int, steps: int) -> dict:
+    """Batch of simple cubic samples (FP64 form; nu = 1/2, W = 1, xi = 1, rc = 4, T = 0.05,
+    E = 0.005) from the random start: one untimed step of `hops` hops per sample, then `steps`
+    timed steps; beside it the 3D oracle on one sample of the batch, single core."""
+    import oracle
+    from workloads import Sample
+
+    samples = [Sample(L, L ** 3 // 2, 1.0, 1.0, 4.0, 0.05, 0.005, 13, b, dim=3) for b in range(batch)]
+    b = cg.Batch(samples, cg.make_opts(precision=cg.CG_FP64))
+    b.run_hops(hops)
+    torch.cuda.synchronize()
+    b.kernel_time()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run_hops(hops)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hop_ms, hop_n, _, _ = b.kernel_time()
+    st = [b.stats(k) for k in range(batch)]
+    b.close()
+    s = samples[0]
+    o = oracle.Oracle3D(L=L, n_e=s.n_e, W=s.W, xi=s.xi, rc=s.rc, T=s.T, E=s.E, seed=s.seed, sample_id=0)
+    o.run(hops)
+    n_cpu = max(64, hops // 8)
+    c0 = time.perf_counter()
+    o.run(n_cpu)
+    cpu = n_cpu / (time.perf_counter() - c0)
+    m_bar = sum(x["s_last"] for x in st) / sum(x["hops"] for x in st)
+    return {"L": L, "N": L ** 3, "batch": batch, "rc": 4.0, "T": 0.05, "E": 0.005, "hops_per_step": hops,
+            "steps": steps, "hops_per_s": batch * hops * steps / dt, "mean_launch_ms": hop_ms / max(hop_n, 1),
+            "m_bar": m_bar, "cpu_oracle_one_core_hops_per_s": cpu,
+            "cpu_sample": f"3D oracle, sample 0, hops {hops}..{hops + n_cpu} after {hops} untimed"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +222,10 @@ def main() -> int:
     ap.add_argument("--large-L", type=int, default=0,
                     help="also time one sample of this side (a power of two, 256..2048) on the whole GPU, FP64")
     ap.add_argument("--large-hops", type=int, default=2000)
+    ap.add_argument("--cubic-L", type=int, default=0,
+                    help="also time a batch of simple cubic samples of this side (FP64 form)")
+    ap.add_argument("--cubic-hops", type=int, default=2048)
+    ap.add_argument("--cubic-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB with a plain device copy (a counter "
                          "calibration point for FETCH_SIZE / WRITE_SIZE runs)")
@@ -280,6 +318,8 @@ def main() -> int:
         out["fp64_ms_per_step"] = r64["seconds"] / args.steps * 1e3
     if args.large_L:
         out["large_lattice_fp64"] = large_lattice(cg, torch, args.large_L, args.large_hops, args.large_hops // 4)
+    if args.cubic_L:
+        out["cubic_fp64"] = cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps)
     if not args.skip_cpu:
         cores = args.cpu_cores or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(args.warmup * args.hops_per_step, args.cpu_hops, samples[0].seed, cores)
