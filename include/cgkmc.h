@@ -92,7 +92,7 @@ typedef struct cg_run_opts {
   int32_t use_graph;   /* 1: cg_run_hops captures its launch sequence once per (n_hops,
                           refresh phase) as a hipGraph and replays it; needs a stream
                           other than the legacy default stream                          */
-  int32_t variant;     /* hop kernel: 0 = automatic (3 where it applies, else 1);
+  int32_t variant;     /* hop kernel: 0 = automatic (3 or 5 where they apply, else 1);
                           1 = two workgroup barriers per hop, any L;
                           2 = one barrier per hop (FP32 form, L <= 128: double-buffered
                           energies, the next round corrects for the hop in flight);
@@ -101,7 +101,11 @@ typedef struct cg_run_opts {
                           hi + lo pairs renormalised every 16 hops, precomputed
                           acceptance thresholds;
                           4 = whole-GPU kernel (FP64, L a power of two >= 128): each
-                          sample on every CU, automatic for L > 192                     */
+                          sample on every CU, automatic for L > 192;
+                          5 = exact-geometry FP64 kernel (every sample L = 64, or every
+                          sample L = 128; M <= 1024, deterministic clock): energies in
+                          registers, value words in LDS, triangle-ordered FP64 table;
+                          the same hops as 1                                            */
   int32_t reserved;    /* set to 0                                                       */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;

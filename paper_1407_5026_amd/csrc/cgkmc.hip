@@ -18,6 +18,7 @@
 #include "hop3d.hpp"
 #include "hop_big.hpp"
 #include "hop_fx.hpp"
+#include "hop_fx64.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 #include "observables.hpp"
@@ -131,7 +132,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, int
     while (o < n_orb - 1 && w >= (uint64_t)t.thr[o]) ++o;
     t.guide[k] = (uint8_t)o;
   }
-  if (layout == kRaw || layout == kBig) {
+  if (layout == kRaw || layout == kBig || layout == kFx64) {
     // 16-bit guide: a bucket [w, w + 2^22) needs the threshold search only if some
     // threshold of an orbit before the last lies strictly inside it
     t.guide16.assign(kGuideSize, 0);
@@ -167,7 +168,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, int
       const int32_t r2 = ax * ax + ay * ay;
       t.tab64[(size_t)ay * H1 + ax] = r2 == 0 ? 0.0 : 1.0 / std::sqrt((double)r2);
     }
-  const size_t nk = layout == kTri ? (size_t)tri_entries(H)
+  const size_t nk = (layout == kTri || layout == kFx64) ? (size_t)tri_entries(H)
                     : layout == kRaw ? (size_t)fx_tab_entries(L, fx_waves) : layout == kBig ? 0 : (size_t)full_entries(H);
   std::vector<double> k64(nk, 0.0);
   if (layout == kRaw) {
@@ -181,7 +182,7 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, int
     for (int32_t ay = 0; ay < H1; ++ay)
       for (int32_t ax = 0; ax < H1; ++ax) {
         size_t idx;
-        if (layout == kTri) {
+        if (layout == kTri || layout == kFx64) {
           const int32_t a = std::max(ay, ax), b = std::min(ay, ax);
           idx = (size_t)(a * (a + 1) / 2 + b);
         } else {
@@ -247,7 +248,7 @@ struct SampleLayout {
 struct Plan {
   int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0, timers = 0;
   int32_t use_graph = 0, variant = 0;
-  bool use_db = false, use_fx = false;
+  bool use_db = false, use_fx = false, use_fx64 = false;
   bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
@@ -484,7 +485,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.timers = o->phase_timers;
   if (o->use_graph != 0 && o->use_graph != 1) return set_err(CG_EINVAL, "use_graph=%d", o->use_graph);
   p.use_graph = o->use_graph;
-  if (o->variant < 0 || o->variant > 4) return set_err(CG_EINVAL, "variant=%d", o->variant);
+  if (o->variant < 0 || o->variant > 5) return set_err(CG_EINVAL, "variant=%d", o->variant);
   p.variant = o->variant;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
@@ -553,6 +554,16 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   const bool fx_ok = !p.big && p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
                      need_fx <= lds_cap;
   p.use_fx = fx_ok && (p.variant == 0 || p.variant == 3);
+  // exact-geometry FP64 kernel: the same lattices in the FP64 form
+  const int32_t need_fx64 = fx64_lds(s[0].L, max_orb).total;
+  // (deterministic clock and chunks of 1024 labels: the other forms need more registers
+  // than the kernel keeps free, and run on the generic kernel)
+  const bool fx64_ok = !p.big && p.precision == CG_FP64 && same_L && (s[0].L == 64 || s[0].L == 128) &&
+                       need_fx64 <= lds_cap && p.block == 1024 && p.U == 1 && p.clock == CG_CLOCK_DET;
+  p.use_fx64 = fx64_ok && (p.variant == 0 || p.variant == 5);
+  if (p.variant == 5 && !p.use_fx64)
+    return set_err(CG_EINVAL, "variant 5 (exact-geometry FP64 kernel) needs the FP64 form, one L in {64, 128} "
+                   "for all samples, M <= 1024, the deterministic clock and %d bytes of LDS", need_fx64);
   if (p.variant == 3 && !p.use_fx)
     return set_err(CG_EINVAL, "variant 3 (exact-geometry kernel) needs the FP32 form, one L in {64, 128} "
                    "for all samples and %d bytes of LDS", need_fx);
@@ -566,6 +577,9 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (p.big) {
     p.layout = kBig;
     p.lds_hop = big_lds(max_orb).total;
+  } else if (p.use_fx64) {
+    p.layout = kFx64;
+    p.lds_hop = need_fx64;
   } else if (p.use_fx) {
     p.layout = kRaw;
     p.lds_hop = need_fx;
@@ -597,10 +611,10 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   for (int32_t b = 0; b < n; ++b) {
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
-    const int32_t ntab = p.layout == kTri ? tri_entries(H)
+    const int32_t ntab = (p.layout == kTri || p.layout == kFx64) ? tri_entries(H)
                          : p.layout == kRaw ? fx_tab_entries(L, p.block / 64) : p.layout == kBig ? 0 : full_entries(H);
     const int32_t nblk = (N + kInitBlock - 1) / kInitBlock;
-    const bool bigl = p.layout == kBig, sel16 = p.layout == kRaw || bigl;
+    const bool bigl = p.layout == kBig, sel16 = p.layout == kRaw || p.layout == kFx64 || bigl;
     max_L = std::max(max_L, L);
     SampleLayout& q = p.sl[b];
     // refresh by Fourier transform when every thread's outputs fit its registers and a
@@ -700,6 +714,7 @@ HopFn pick_fx(int32_t U, int32_t NC, int32_t NW) {
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
               int32_t block) {
   if (layout == kCube) return k_hops3;
+  if (layout == kFx64) return NC == 1 ? k_hops_fx64<64, 1, 0> : k_hops_fx64<128, 1, 0>;
   if (layout == kRaw)
     return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);
   if (db) return pick_db(U, NC, exact);
@@ -1006,7 +1021,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     std::memcpy(base + q.orb, t.orb.data(), t.orb.size() * 4);
     std::memcpy(base + q.vec, t.vec.data(), t.vec.size() * 4);
     std::memcpy(base + q.guide, t.guide.data(), t.guide.size());
-    if (p.layout == kRaw || p.layout == kBig) {
+    if (p.layout == kRaw || p.layout == kBig || p.layout == kFx64) {
       std::memcpy(base + q.vec8, t.vec8.data(), t.vec8.size() * 4);
       std::memcpy(base + q.guide16, t.guide16.data(), t.guide16.size() * 2);
     }
@@ -1023,7 +1038,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.NW = (N + 31) / 32;
     s.n_orb = t.n_orb;
     s.n_vec = t.n_vec;
-    s.ntab = p.layout == kTri    ? tri_entries(t.H)
+    s.ntab = (p.layout == kTri || p.layout == kFx64) ? tri_entries(t.H)
              : p.layout == kRaw  ? fx_tab_entries(L, p.block / 64)
              : p.layout == kCube ? (t.H + 1) * (t.H + 1) * (t.H + 1)
                                  : full_entries(t.H);

@@ -34,7 +34,7 @@ constexpr int kInitBlock = 256;     // threads per block of the init / refresh k
 // FP32 kernel's table by raw row difference dy + L and folded column distance (see fx_pitch).
 // kBig: the large-sample kernel (one sample on the whole GPU): the FP64 (|dy|, |dx|) table in
 // global memory, no kernel table.
-enum TableLayout : int32_t { kFull = 0, kTri = 1, kRaw = 2, kBig = 3, kCube = 4 };
+enum TableLayout : int32_t { kFull = 0, kTri = 1, kRaw = 2, kBig = 3, kCube = 4, kFx64 = 5 };
 
 struct SampleState {
   uint64_t s_last;        // label of the last executed hop

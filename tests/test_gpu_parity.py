@@ -479,3 +479,31 @@ def test_label_cap_stall_then_resume():
     assert compare_logs(s, b.hop_log(0), o.run(n)) == n
     assert float(np.abs(b.energies(0) - o.eps()).max()) <= 1e-12
     say(f"label cap: {stalls} stalled calls, {n} hops equal to the oracle")
+
+
+@pytest.mark.parametrize("L", [64, 128])
+def test_fp64_exact_geometry_kernel(L):
+    """The exact-geometry FP64 kernel (variant 5; automatic for these lattices) executes the
+    oracle's hops with the oracle's energies, and the same hops, energies and counters as the
+    generic FP64 kernel (variant 1), bit for bit."""
+    cg = require_gpu()
+    from workloads import headline
+
+    samples = headline(3, seed=29) if L == 128 else [Sample(64, 2048, 1.0, 1.0, 8.0, 0.05, 0.01, 29, b)
+                                                      for b in range(3)]
+    hops = 1500
+    b5 = _batch(cg, samples, precision=cg.CG_FP64, log_hops=hops, variant=5)
+    b1 = _batch(cg, samples, precision=cg.CG_FP64, log_hops=hops, variant=1)
+    b5.run_hops(hops)
+    b1.run_hops(hops)
+    for k, s in enumerate(samples):
+        for x, y in zip(b5.hop_log(k), b1.hop_log(k)):
+            assert np.array_equal(x, y)
+        assert np.array_equal(b5.energies(k), b1.energies(k))
+        s5, s1 = b5.stats(k), b1.stats(k)
+        for f in ("hops", "s_last", "s_scan", "P", "t", "H0", "sum_p", "theta_pass"):
+            assert s5[f] == s1[f], (k, f)
+    o = oracle_of(samples[0])
+    assert compare_logs(samples[0], b5.hop_log(0), o.run(hops)) == hops
+    assert float(np.abs(b5.energies(0) - o.eps()).max()) <= 1e-12
+    say(f"FP64 exact-geometry kernel L={L}: {hops} hops equal to the generic kernel and the oracle")
