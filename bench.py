@@ -210,7 +210,7 @@ def main() -> int:
     ap.add_argument("--window-hops", type=int, default=98304)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--hops-per-step", type=int, default=4096)
-    ap.add_argument("--M", type=int, default=1024)
+    ap.add_argument("--M", type=int, default=8192)
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--clock", type=int, default=0,

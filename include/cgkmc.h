@@ -103,9 +103,9 @@ typedef struct cg_run_opts {
                           4 = whole-GPU kernel (FP64, L a power of two >= 128): each
                           sample on every CU, automatic for L > 192;
                           5 = exact-geometry FP64 kernel (every sample L = 64, or every
-                          sample L = 128; M <= 1024, deterministic clock): energies in
-                          registers, value words in LDS, triangle-ordered FP64 table;
-                          the same hops as 1                                            */
+                          sample L = 128; deterministic clock; chunks of 1024 labels for
+                          any M): energies in registers, value words in LDS, triangle-
+                          ordered FP64 table; the same hops as 1                        */
   int32_t reserved;    /* set to 0                                                       */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;

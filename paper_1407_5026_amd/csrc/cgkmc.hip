@@ -556,14 +556,15 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.use_fx = fx_ok && (p.variant == 0 || p.variant == 3);
   // exact-geometry FP64 kernel: the same lattices in the FP64 form
   const int32_t need_fx64 = fx64_lds(s[0].L, max_orb).total;
-  // (deterministic clock and chunks of 1024 labels: the other forms need more registers
-  // than the kernel keeps free, and run on the generic kernel)
+  // (deterministic clock: the stochastic clocks' calls need more registers than the kernel
+  // keeps free, and run on the generic kernel; it evaluates chunks of 1024 labels for any M)
   const bool fx64_ok = !p.big && p.precision == CG_FP64 && same_L && (s[0].L == 64 || s[0].L == 128) &&
-                       need_fx64 <= lds_cap && p.block == 1024 && p.U == 1 && p.clock == CG_CLOCK_DET;
+                       need_fx64 <= lds_cap && p.block == 1024 && p.clock == CG_CLOCK_DET;
   p.use_fx64 = fx64_ok && (p.variant == 0 || p.variant == 5);
   if (p.variant == 5 && !p.use_fx64)
     return set_err(CG_EINVAL, "variant 5 (exact-geometry FP64 kernel) needs the FP64 form, one L in {64, 128} "
-                   "for all samples, M <= 1024, the deterministic clock and %d bytes of LDS", need_fx64);
+                   "for all samples, the deterministic clock and %d bytes of LDS", need_fx64);
+  if (p.use_fx64) p.U = 1;
   if (p.variant == 3 && !p.use_fx)
     return set_err(CG_EINVAL, "variant 3 (exact-geometry kernel) needs the FP32 form, one L in {64, 128} "
                    "for all samples and %d bytes of LDS", need_fx);
