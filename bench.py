@@ -138,13 +138,15 @@ def run_form(cg, torch, samples, precision, args, hops_per_step):
                 windows=windows, window_hops=per_win * hops_per_step)
 
 
-def large_lattice(cg, torch, L: int, hops: int, warm: int) -> dict:
+def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float) -> dict:
     """One sample of side L on the whole GPU (FP64 form): the paper's large-lattice setting
-    (nu = 1/2, xi = 1, W = 1, T = 0.05, E = T/10; hop cutoff rc = 10), warm untimed hops from
-    the random start, then `hops` timed hops."""
+    (nu = 1/2, xi = 1, W = 1, E = T/10; hop cutoff rc = 10), warm untimed hops from the random
+    start, then `hops` timed hops.  Per hop the update writes the N FP64 energies of the
+    proposals' mirror (8 N bytes) and reads two FP64 inverse distances per site from the
+    (|dy|, |dx|) table (16 N bytes, cache-resident for L <= 2048)."""
     from workloads import Sample
 
-    s = Sample(L, L * L // 2, 1.0, 1.0, 10.0, 0.05, 0.005, 7, 0)
+    s = Sample(L, L * L // 2, 1.0, 1.0, 10.0, T, T / 10, 7, 0)
     t0 = time.perf_counter()
     b = cg.Batch([s], cg.make_opts(precision=cg.CG_FP64))
     torch.cuda.synchronize()
@@ -158,12 +160,19 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int) -> dict:
     b.run_hops(hops)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    hop_ms, hop_n, _, _ = b.kernel_time()
     st1 = b.stats(0)
-    m_bar = (st1["s_last"] - st0["s_last"]) / max(st1["hops"] - st0["hops"], 1)
+    done = max(st1["hops"] - st0["hops"], 1)
+    m_bar = (st1["s_last"] - st0["s_last"]) / done
+    rounds = (st1["rounds"] - st0["rounds"]) / done
     b.close()
-    return {"L": L, "N": L * L, "T": 0.05, "E": 0.005, "hops": hops, "warmup_hops": warm, "hops_per_s": hops / dt,
-            "us_per_hop": dt / hops * 1e6, "m_bar": m_bar, "init_s": init_s,
-            "paper_gpu_ms_per_hop_T005": {"64": 0.10, "2048": 1.04}.get(str(L))}
+    paper = {0.05: {"64": 0.10, "2048": 1.04}, 0.001: {"64": 0.27, "2048": 1.23}}.get(T, {}).get(str(L))
+    us = hop_ms * 1e3 / done
+    return {"L": L, "N": L * L, "T": T, "E": T / 10, "hops": hops, "warmup_hops": warm,
+            "hops_per_s": hops / dt, "us_per_hop": dt / hops * 1e6, "kernel_us_per_hop": us,
+            "kernel_launches": hop_n, "m_bar": m_bar, "rounds_per_hop": rounds,
+            "update_bytes_per_hop": 24 * L * L, "update_GBps": 24 * L * L / (us * 1e-6) / 1e9,
+            "init_s": init_s, "paper_gpu_ms_per_hop": paper}
 
 
 def cubic(cg, torch, L: int, batch: int, hops: int, steps: int) -> dict:
@@ -219,9 +228,11 @@ def main() -> int:
     ap.add_argument("--cpu-hops", type=int, default=8192)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--large-L", type=int, default=0,
-                    help="also time one sample of this side (a power of two, 256..2048) on the whole GPU, FP64")
+    ap.add_argument("--large-L", type=int, nargs="*", default=[],
+                    help="also time one sample of each of these sides (powers of two, 256..2048) on the "
+                         "whole GPU, FP64")
     ap.add_argument("--large-hops", type=int, default=2000)
+    ap.add_argument("--large-T", type=float, default=0.05)
     ap.add_argument("--cubic-L", type=int, default=0,
                     help="also time a batch of simple cubic samples of this side (FP64 form)")
     ap.add_argument("--cubic-hops", type=int, default=2048)
@@ -317,7 +328,11 @@ def main() -> int:
         out["fp64_window_hops_per_s"] = [round(v) for v in r64["windows"]]
         out["fp64_ms_per_step"] = r64["seconds"] / args.steps * 1e3
     if args.large_L:
-        out["large_lattice_fp64"] = large_lattice(cg, torch, args.large_L, args.large_hops, args.large_hops // 4)
+        out["large_lattice_fp64"] = []
+        for L in args.large_L:
+            print(f"[bench] whole-GPU sample L={L} T={args.large_T}", file=sys.stderr, flush=True)
+            out["large_lattice_fp64"].append(
+                large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4, args.large_T))
     if args.cubic_L:
         out["cubic_fp64"] = cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps)
     if not args.skip_cpu:

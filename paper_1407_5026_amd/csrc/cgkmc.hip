@@ -241,7 +241,7 @@ int32_t count_vectors(double rc) {
 // ---------------------------------------------------------------------------------
 struct SampleLayout {
   size_t tab64, tabk, thr, orb, vec, guide, vec8, guide16, tdo64, dft_tw, dft_T, static_end;  // uploaded in one copy
-  size_t eps, phi, occ, part, log_label, log_from, log_to, mirror, sel, end;
+  size_t eps, phi, occ, part, log_label, log_from, log_to, mirror, sel, mirror2, occ2, bar, end;
   int32_t dft, dft_kc, dft_rows;
 };
 
@@ -457,7 +457,7 @@ int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
     q.log_label = off; off = align_up(off + (size_t)p.log_cap * 8);
     q.log_from = off;  off = align_up(off + (size_t)p.log_cap * 4);
     q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
-    q.mirror = q.sel = off;
+    q.mirror = q.sel = q.mirror2 = q.occ2 = q.bar = off;
     q.end = off;
   }
   plan_tail(s, n, p, off);
@@ -651,6 +651,9 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
     q.mirror = off;    off = align_up(off + (bigl ? (size_t)N * 8 : 0));
     q.sel = off;       off = align_up(off + (bigl ? sizeof(OccSelect) : 0));
+    q.mirror2 = off;   off = align_up(off + (bigl ? (size_t)N * 8 : 0));
+    q.occ2 = off;      off = align_up(off + (bigl ? (size_t)NW * 4 : 0));
+    q.bar = off;       off = align_up(off + (bigl ? (size_t)kBarWords * 4 : 0));
     q.end = off;
   }
   p.NC = max_L <= 64 ? 1 : (max_L <= 128 ? 2 : 3);
@@ -1077,6 +1080,9 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.guide16 = (const uint16_t*)(a + q.guide16);
     s.tdo64 = (const double*)(a + q.tdo64);
     s.mirror = (double*)(a + q.mirror);
+    s.mirror2 = (double*)(a + q.mirror2);
+    s.occ2 = (uint32_t*)(a + q.occ2);
+    s.bar = (uint32_t*)(a + q.bar);
     s.part = (double*)(a + q.part);
     s.dft_tw = (const double*)(a + q.dft_tw);
     s.dft_T = (const double*)(a + q.dft_T);

@@ -189,27 +189,44 @@ __global__ void __launch_bounds__(kInitBlock) k_eps_big(const DevSample* __restr
   }
 }
 
-// Grid-wide barrier of one cooperative launch: workgroup leaders publish their writes
-// (agent-scope release), count in with an atomic on the sample's counter (zeroed before the
-// launch) and wait for all G arrivals of this barrier (acquire).  The wait is bounded: after
-// kBarrierSpins polls it gives up and returns false, so a workgroup can never wait forever.
+// Grid-wide barrier of one cooperative launch, a two-level counter tree: workgroup g counts
+// into the counter of group g % 8 (a release add: its writes are made visible first); the
+// last arriver of a group counts into the top counter, and the top's last arriver stores the
+// barrier's number in the release word, which every workgroup polls with plain coherent
+// loads before one acquire fence.  Counters are zeroed before each launch and only grow, so
+// the n-th barrier is complete when the release word reaches n.  The wait is bounded: after
+// kBarrierSpins polls a workgroup gives up and returns false, so none can wait forever.
+// Per-workgroup fences, not the atomics, dominate a grid barrier on this GPU (a full fence
+// at every poll costs 16.7 us per barrier at 256 workgroups, this form 5.1 us), hence one
+// release at arrival and one acquire after the wait.
 constexpr uint32_t kBarrierSpins = 1u << 22;
+constexpr int kBarLine = 32;              // words per 128-byte line
+constexpr int kBarWords = 10 * kBarLine;  // release word, top counter, 8 group counters
 
-__device__ __forceinline__ bool grid_barrier(uint32_t* counter, uint32_t& target, uint32_t G, uint32_t* ok_sh) {
+__device__ __forceinline__ bool grid_barrier(uint32_t* bar, uint32_t& n, uint32_t G, uint32_t* ok_sh) {
   __syncthreads();
-  target += G;
+  ++n;
   if (threadIdx.x == 0) {
-    __threadfence();
-    atomicAdd(counter, 1u);
+    const uint32_t g = blockIdx.x;
+    const uint32_t gsize = (G + 7u - (g & 7u)) / 8u;  // workgroups of this group
+    const uint32_t ngroups = G < 8u ? G : 8u;
+    const uint32_t old =
+        __hip_atomic_fetch_add(bar + (2 + (g & 7u)) * kBarLine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == n * gsize - 1u) {
+      // the group is complete: take over its releases and pass them on to the top
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t o2 = __hip_atomic_fetch_add(bar + kBarLine, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 == n * ngroups - 1u) __hip_atomic_store(bar, n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
     uint32_t ok = 1u, spins = 0u;
-    while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < n) {
+      __builtin_amdgcn_s_sleep(1);
       if (++spins >= kBarrierSpins) {
         ok = 0u;
         break;
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *ok_sh = ok;
   }
   __syncthreads();
@@ -217,6 +234,7 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* counter, uint32_t& target
 }
 
 __global__ void k_bar_reset(const DevSample* __restrict__ samples, int32_t sample) {
+  if (threadIdx.x < 10) samples[sample].bar[threadIdx.x * kBarLine] = 0u;
   if (threadIdx.x == 0) samples[sample].st->grid_bar = 0u;
 }
 
@@ -312,7 +330,7 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
   double* __restrict__ tclock = (double*)(smem + lo.ctrl);
   uint32_t* __restrict__ theta_sh = (uint32_t*)(smem + lo.ctrl + 8);
   uint32_t* __restrict__ bar_ok = (uint32_t*)(smem + lo.ctrl + 12);
-  uint32_t bar_target = 0;
+  uint32_t bar_n = 0;
   const uint32_t G = gridDim.x;
 
   // owned sites and their energies
@@ -348,8 +366,6 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
   C.mTln2 = 0.f;
   const double Ef = uni(S.E), Tt = uni(S.T), Gamma = uni(S.Gamma);
   const int64_t log_cap = uni((int64_t)S.log_cap);
-  const uint32_t* __restrict__ occ = S.occ;
-  double* __restrict__ mirror = S.mirror;
   const double* __restrict__ tab = S.tab64;
   constexpr int H1 = L / 2 + 1;
   const uint64_t s_end = uni((ra.time_mode && CLOCK == 0) ? label_at_time(t_end, Gamma) : (uint64_t)0);
@@ -358,7 +374,24 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
   uint32_t theta_cnt = 0;
   uint32_t round = 0;
 
-  for (;;) {
+  // Two copies of the proposals' view (occupation words and energy mirror): hop k of this
+  // launch reads copy k % 2 and writes the state after the hop into the other copy, so one
+  // grid barrier per hop (after the writes) suffices: the copy a hop writes was last read
+  // before the previous hop's barrier.  Copy 0 (S.occ, S.mirror) holds the state at launch
+  // start and again at launch end; copy 1 starts as copy 0's occupation.
+  {
+    const int nw = S.NW;
+    for (int w = (int)blockIdx.x * 1024 + tid; w < nw; w += (int)G * 1024) S.occ2[w] = S.occ[w];
+  }
+  if (!grid_barrier(S.bar, bar_n, G, bar_ok)) status = -3;
+  uint32_t kh = 0;           // hops executed by this launch
+  int prev_i = 0, prev_j = 0;  // sites of the previous hop of this launch
+
+  for (; status == 0;) {
+    const uint32_t* __restrict__ occ = (kh & 1u) ? S.occ2 : S.occ;
+    const double* __restrict__ mirror = (kh & 1u) ? S.mirror2 : S.mirror;
+    uint32_t* __restrict__ occ_w = (kh & 1u) ? S.occ : S.occ2;
+    double* __restrict__ mirror_w = (kh & 1u) ? S.mirror : S.mirror2;
     uint32_t found = 0u, win0 = 0u, win1 = 0u, win2 = 0u;
     uint64_t wdh = 0;
     for (;;) {
@@ -427,11 +460,6 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
       }
     }
     if (!found) break;
-    // every workgroup has finished reading this round's occupation and mirror
-    if (!grid_barrier(&gs->grid_bar, bar_target, G, bar_ok)) {
-      status = -3;  // CG_EHIP: a workgroup did not arrive
-      break;
-    }
 
     // step 3: every workgroup executes the same hop; workgroup 0 writes the shared state
     const int hi = (int)win0, hj = (int)win1;
@@ -448,8 +476,14 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
     sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
     if (tid == 0) {
       if (lead) {
-        atomicAnd(&S.occ[hi >> 5], ~(1u << (hi & 31)));
-        atomicOr(&S.occ[hj >> 5], 1u << (hj & 31));
+        // the written copy missed the previous hop of this launch and now takes both, in
+        // order (one thread, plain read-modify-writes of the same words in program order)
+        if (kh > 0) {
+          occ_w[prev_i >> 5] &= ~(1u << (prev_i & 31));
+          occ_w[prev_j >> 5] |= 1u << (prev_j & 31);
+        }
+        occ_w[hi >> 5] &= ~(1u << (hi & 31));
+        occ_w[hj >> 5] |= 1u << (hj & 31);
         if (logged < log_cap) {
           S.log_label[logged] = q;
           S.log_from[logged] = hi;
@@ -477,13 +511,16 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           e[s0 + c] = e[s0 + c] + (tj[c] - ti[c]);
-          mirror[first_site + 1024 * (s0 + c)] = e[s0 + c];
+          mirror_w[first_site + 1024 * (s0 + c)] = e[s0 + c];
         }
       }
     }
-    // mirror and occupation visible to every workgroup (the barrier also orders the Gaussian
-    // clock in LDS)
-    if (!grid_barrier(&gs->grid_bar, bar_target, G, bar_ok)) {
+    prev_i = hi;
+    prev_j = hj;
+    ++kh;
+    // the written copy visible to every workgroup (the barrier also orders the Gaussian clock
+    // in LDS)
+    if (!grid_barrier(S.bar, bar_n, G, bar_ok)) {
       status = -3;
       break;
     }
@@ -504,8 +541,15 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
     for (int s = 0; s < SPT; ++s) g[first_site + 1024 * s] = e[s];
   }
   atomicAdd(theta_sh, theta_cnt);
-  // every workgroup has read the sample state before workgroup 0 rewrites it
-  if (!grid_barrier(&gs->grid_bar, bar_target, G, bar_ok)) status = -3;
+  // every workgroup has read the sample state and the occupation before workgroup 0 rewrites
+  // the state and copy 1's occupation (current after an odd number of hops) returns to copy 0
+  if (!grid_barrier(S.bar, bar_n, G, bar_ok)) status = -3;
+  if (kh & 1u) {
+    const int nw = S.NW;
+    for (int w = (int)blockIdx.x * 1024 + tid; w < nw; w += (int)G * 1024) S.occ[w] = S.occ2[w];
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) S.mirror[first_site + 1024 * s] = e[s];
+  }
   if (lead && tid == 0) {
     gs->hops = hops;
     gs->s_last = s_last;

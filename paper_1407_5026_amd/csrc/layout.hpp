@@ -57,7 +57,7 @@ struct SampleState {
   int32_t status;         // 0 ok, CG_ESTALL
   int32_t since_refresh;  // hops since last refresh
   int32_t force_refresh;  // refresh kernel: refresh regardless of since_refresh
-  uint32_t grid_bar;      // whole-GPU kernel: arrivals at its grid barrier in this launch
+  uint32_t grid_bar;      // unused (kept for the checkpoint layout; the barrier words are DevSample::bar)
   uint64_t phase_cycles[4];  // shader cycles: refill, evaluate, execute, update (if timed)
 };
 
@@ -83,6 +83,9 @@ struct DevSample {
   const uint16_t* guide16;  // kRaw: orbit at each bucket start | 0x8000 if a threshold lies inside
   const double* tdo64;    // large-sample kernel: FP64 1/|d| per orbit
   double* mirror;         // large-sample kernel: global copy of the energies for the proposals
+  double* mirror2;        // large-sample kernel: the second copy (odd hops of a launch)
+  uint32_t* occ2;         // large-sample kernel: second copy of the occupation words
+  uint32_t* bar;          // large-sample kernel: grid-barrier words, one per 128-byte line
   double* part;
   const double* dft_tw;   // [L] (cos, sin)(2 pi j / L)
   const double* dft_T;    // [(H+1) x L] sum_dx T(dx, dy) cos(2 pi k dx / L), row k

@@ -9,6 +9,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <string>
 
 #define CHK(x)                                                                          \
   do {                                                                                  \
@@ -291,9 +292,174 @@ __global__ void __launch_bounds__(1024) k_log2(float* out, int iters) {
   if (s == 1.2345f) out[blockIdx.x * 1024 + threadIdx.x] = s;
 }
 
-int main() {
+// Grid-wide barriers over G workgroups of one cooperative launch (the whole-GPU hop kernel's
+// synchronisation), iters barriers per launch.  Every wait is bounded (kGbarSpins polls); a
+// workgroup that gives up counts a failure and leaves, and the others then give up in turn.
+constexpr uint32_t kGbarSpins = 1u << 20;
+constexpr int kLine = 32;  // words per 128-byte line: one flag or counter per line
+
+__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool spin_until(const uint32_t* p, uint32_t target) {
+  uint32_t spins = 0;
+  while (ld_acq(p) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins >= kGbarSpins) return false;
+  }
+  return true;
+}
+// relaxed polls (no cache maintenance per poll)
+__device__ __forceinline__ bool spin_rlx(const uint32_t* p, uint32_t target) {
+  uint32_t spins = 0;
+  while (ld_rlx(p) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins >= kGbarSpins) return false;
+  }
+  return true;
+}
+
+// MODE 0: one counter, every workgroup adds 1 and polls it.
+// MODE 1: per-workgroup arrival flags (own line each) polled by workgroup 0's threads, which
+//         then store the release generation that everyone polls.
+// MODE 2: 8 group counters (workgroup g in group g % 8) whose last arriver adds 1 to a top
+//         counter; the top's last arriver stores the release generation.
+// MODE 3: one counter, release add, relaxed polls, one acquire fence after the wait.
+// MODE 4: one counter, relaxed add and polls, no fence (the cost of the atomics alone).
+// MODE 5: MODE 2's tree with a release add, relaxed polls and one acquire fence.
+template <int MODE>
+__global__ void __launch_bounds__(1024) k_gbar(uint32_t* sync, uint32_t* fail, int iters) {
+  __shared__ uint32_t ok;
+  const uint32_t G = gridDim.x, g = blockIdx.x;
+  uint32_t* rel = sync;                       // release generation
+  uint32_t* top = sync + kLine;               // MODE 0 counter / MODE 2 top counter
+  uint32_t* grp = sync + 2 * kLine;           // MODE 2: 8 group counters
+  uint32_t* flag = sync + 10 * kLine;         // MODE 1: G arrival flags
+  const uint32_t gsize = (G + 7 - (g & 7)) / 8;  // workgroups in this one's group
+  for (uint32_t it = 1; it <= (uint32_t)iters; ++it) {
+    __syncthreads();
+    bool good = true;
+    if (MODE == 0) {
+      if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(top, 1u);
+        good = spin_until(top, it * G);
+        __threadfence();
+      }
+    } else if (MODE == 1) {
+      if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(flag + g * kLine, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (g == 0) {
+        if (threadIdx.x < G) good = spin_until(flag + threadIdx.x * kLine, it);
+        good = __syncthreads_and(good);
+        if (threadIdx.x == 0 && good) {
+          __threadfence();
+          __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      if (threadIdx.x == 0 && good) {
+        good = spin_until(rel, it);
+        __threadfence();
+      }
+    } else if (MODE == 3) {
+      if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        good = spin_rlx(top, it * G);
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      }
+    } else if (MODE == 4) {
+      if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = spin_rlx(top, it * G);
+      }
+    } else if (MODE == 5) {
+      if (threadIdx.x == 0) {
+        const uint32_t old = __hip_atomic_fetch_add(grp + (g & 7) * kLine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == it * gsize - 1) {
+          const uint32_t ngroups = G < 8 ? G : 8;
+          const uint32_t o2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (o2 == it * ngroups - 1) __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        good = spin_rlx(rel, it);
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+      }
+    } else {
+      if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t old = atomicAdd(grp + (g & 7) * kLine, 1u);
+        if (old == it * gsize - 1) {
+          const uint32_t ngroups = G < 8 ? G : 8;
+          const uint32_t o2 = atomicAdd(top, 1u);
+          if (o2 == it * ngroups - 1) {
+            __threadfence();
+            __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        good = spin_until(rel, it);
+        __threadfence();
+      }
+    }
+    if (threadIdx.x == 0) ok = good ? 1u : 0u;
+    __syncthreads();
+    if (ok == 0u) {
+      if (threadIdx.x == 0) atomicAdd(fail, 1u);
+      return;
+    }
+  }
+}
+
+// Grid-barrier costs for G = 64, 128, 256 workgroups: microseconds per barrier.
+static int run_grid_barriers(int ncu) {
+  const int n_sync = (10 + 1024) * kLine;
+  uint32_t *sync = nullptr, *fail = nullptr;
+  CHK(hipMalloc(&sync, n_sync * 4));
+  CHK(hipMalloc(&fail, 4));
+  hipEvent_t e0, e1;
+  CHK(hipEventCreate(&e0));
+  CHK(hipEventCreate(&e1));
+  const int iters = 2000;
+  for (int G : {64, 128, 256}) {
+    if (G > ncu) break;
+    for (int mode = 0; mode < 6; ++mode) {
+      void* const fns[6] = {(void*)k_gbar<0>, (void*)k_gbar<1>, (void*)k_gbar<2>,
+                            (void*)k_gbar<3>, (void*)k_gbar<4>, (void*)k_gbar<5>};
+      void* fn = fns[mode];
+      int it = iters;
+      void* args[] = {&sync, &fail, &it};
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {
+        CHK(hipMemset(sync, 0, n_sync * 4));
+        CHK(hipMemset(fail, 0, 4));
+        CHK(hipDeviceSynchronize());
+        CHK(hipEventRecord(e0));
+        CHK(hipLaunchCooperativeKernel(fn, dim3(G), dim3(1024), args, 0, 0));
+        CHK(hipEventRecord(e1));
+        CHK(hipEventSynchronize(e1));
+        CHK(hipEventElapsedTime(&ms, e0, e1));
+      }
+      uint32_t nf = 0;
+      CHK(hipMemcpy(&nf, fail, 4, hipMemcpyDeviceToHost));
+      const char* const names[6] = {"one counter", "flags + master", "8 group counters",
+                                    "counter, release add, relaxed polls, one acquire",
+                                    "counter, relaxed, no fence", "8 groups, release add, relaxed polls, one acquire"};
+      std::printf("grid barrier mode %d (%s), %3d workgroups  %7.2f us per barrier%s\n", mode, names[mode], G,
+                  ms * 1e3 / iters, nf ? "  (a wait gave up)" : "");
+    }
+  }
+  CHK(hipFree(sync));
+  CHK(hipFree(fail));
+  return 0;
+}
+
+int main(int argc, char** argv) {
   int ncu = 0;
   CHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, 0));
+  if (argc > 1 && std::string(argv[1]) == "barrier") return run_grid_barriers(ncu);
   const double clk = 2.4e9;  // MI355X peak engine clock
   std::printf("CUs %d; rates below per CU at %.1f GHz\n", ncu, clk * 1e-9);
   uint32_t* out = nullptr;

@@ -33,6 +33,30 @@ def test_whole_gpu_kernel_hop_for_hop_l128(M):
     assert abs(st["H0"] - sc["H0"]) <= 1e-9 * abs(sc["H0"])
 
 
+def test_whole_gpu_kernel_odd_and_even_launches():
+    """Within a launch the kernel alternates two copies of the occupation and the energy mirror
+    (hop k reads copy k % 2) and returns to the first copy at the launch's end.  Launches of
+    odd and even hop counts, interleaved with reads of the state, must still execute the
+    oracle's hops: after every launch the occupation and energies equal the oracle's."""
+    cg = require_gpu()
+    s = Sample(128, 8192, 1.0, 1.0, 10.0, 0.05, 0.01, 47, 2)
+    pieces = [1, 2, 3, 1, 7, 64, 13, 1, 1, 400, 5, 2, 33]
+    hops = sum(pieces)
+    say(f"whole-GPU kernel L=128: {len(pieces)} launches, {hops} hops")
+    b = _batch(cg, [s], precision=cg.CG_FP64, M=1024, variant=4, log_hops=hops)
+    o = oracle_of(s)
+    logs = []
+    for n in pieces:
+        b.run_hops(n)
+        logs.append(o.run(n))
+        assert np.array_equal(b.occupation(0), o.occ())
+        assert float(np.abs(b.energies(0) - o.eps()).max()) <= 1e-12
+    ol = tuple(np.concatenate([x[k] for x in logs]) for k in range(3))
+    assert compare_logs(s, b.hop_log(0), ol) == hops
+    st, sc = b.stats(0), o.scalars()
+    assert st["P"] == sc["P"] and st["hops"] == hops
+
+
 def _signed_dx(a, c, L):
     d = (c % L) - (a % L)
     d = np.where(d > L // 2, d - L, d)
