@@ -105,8 +105,16 @@ typedef struct cg_run_opts {
                           5 = exact-geometry FP64 kernel (every sample L = 64, or every
                           sample L = 128; deterministic clock; chunks of 1024 labels for
                           any M): energies in registers, value words in LDS, triangle-
-                          ordered FP64 table; the same hops as 1                        */
-  int32_t reserved;    /* set to 0                                                       */
+                          ordered FP64 table; the same hops as 1;
+                          6 = label-parallel kernel (FP64, L a power of two in [16, 128]):
+                          one sample at a time on `spread` workgroups, each holding a
+                          replica of the sample and evaluating its own 1024 U labels of a
+                          round of spread x 1024 U labels; the round's lowest accepted label
+                          is a global minimum behind one grid barrier (the paper's setting:
+                          one sample, a parallel width of the order of 1/A).  The same hops
+                          as 1 for any spread                                            */
+  int32_t spread;      /* variant 6: workgroups per sample (0 = one per CU; at most the
+                          number that can be co-resident, else CG_ENOSPC); 0 otherwise  */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;
 

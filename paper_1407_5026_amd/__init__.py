@@ -47,7 +47,7 @@ class cg_run_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("M", C.c_int32), ("block", C.c_int32),
                 ("K_refresh", C.c_int32), ("clock_mode", C.c_int32), ("log_hops", C.c_int32),
                 ("phase_timers", C.c_int32), ("use_graph", C.c_int32), ("variant", C.c_int32),
-                ("reserved", C.c_int32), ("max_labels_per_call", C.c_uint64)]
+                ("spread", C.c_int32), ("max_labels_per_call", C.c_uint64)]
 
 
 class cg_stats(C.Structure):
@@ -128,9 +128,9 @@ def _descs(samples):
 
 
 def make_opts(precision=CG_FP64, M=0, block=0, K_refresh=0, clock_mode=CG_CLOCK_DET, log_hops=0,
-              max_labels_per_call=0, phase_timers=0, use_graph=0, variant=0) -> cg_run_opts:
+              max_labels_per_call=0, phase_timers=0, use_graph=0, variant=0, spread=0) -> cg_run_opts:
     return cg_run_opts(precision, M, block, K_refresh, clock_mode, log_hops, phase_timers, use_graph,
-                       variant, 0, max_labels_per_call)
+                       variant, spread, max_labels_per_call)
 
 
 def arena_bytes(samples, opts: cg_run_opts) -> int:

@@ -19,6 +19,7 @@
 #include "hop_big.hpp"
 #include "hop_fx.hpp"
 #include "hop_fx64.hpp"
+#include "hop_wide.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 #include "observables.hpp"
@@ -250,6 +251,8 @@ struct Plan {
   int32_t use_graph = 0, variant = 0;
   bool use_db = false, use_fx = false, use_fx64 = false;
   bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
+  bool wide = false; // one sample at a time on G workgroups, each with a replica (variant 6)
+  int32_t spread = 0;  // wide: workgroups per sample (0 = one per CU)
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
   uint64_t max_labels = 1ull << 32;
@@ -269,6 +272,7 @@ int max_lds_bytes(int32_t* out) {
 }
 
 bool big_eligible(int32_t L) { return L >= 128 && L <= 2048 && (L & (L - 1)) == 0; }
+bool wide_eligible(int32_t L) { return L >= 16 && L <= 128 && (L & (L - 1)) == 0; }
 
 bool is_cube(const cg_sample_desc& d) { return d.dim == 3; }
 int32_t sites_of(const cg_sample_desc& d) { return is_cube(d) ? d.L * d.L * d.L : d.L * d.L; }
@@ -485,8 +489,11 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.timers = o->phase_timers;
   if (o->use_graph != 0 && o->use_graph != 1) return set_err(CG_EINVAL, "use_graph=%d", o->use_graph);
   p.use_graph = o->use_graph;
-  if (o->variant < 0 || o->variant > 5) return set_err(CG_EINVAL, "variant=%d", o->variant);
+  if (o->variant < 0 || o->variant > 6) return set_err(CG_EINVAL, "variant=%d", o->variant);
   p.variant = o->variant;
+  if (o->spread < 0 || (o->spread != 0 && p.variant != 6))
+    return set_err(CG_EINVAL, "spread=%d (workgroups per sample of variant 6, or 0)", o->spread);
+  p.spread = o->spread;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
   if (p.precision == CG_FP64) p.K = 0;
@@ -509,8 +516,20 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   int32_t need_db = 0;
   int32_t max_L_all = 0;
   for (int32_t b = 0; b < n; ++b) max_L_all = std::max(max_L_all, s[b].L);
-  p.big = max_L_all > 192 || p.variant == 4;
-  if (p.big) {
+  p.wide = p.variant == 6;
+  if (p.wide) {
+    for (int32_t b = 0; b < n; ++b) {
+      int rc = validate(s[b], b);
+      if (rc != CG_OK) return rc;
+      if (!wide_eligible(s[b].L))
+        return set_err(CG_EINVAL, "sample %d: L=%d; the label-parallel kernel (variant 6) needs every L a power of two "
+                       "in [16, 128]", b, s[b].L);
+    }
+    if (p.precision != CG_FP64) return set_err(CG_EINVAL, "the label-parallel kernel (variant 6) runs the FP64 form");
+    if (p.use_graph) return set_err(CG_EINVAL, "use_graph is not available with the label-parallel kernel");
+  }
+  p.big = max_L_all > 192 || p.variant == 4 || p.wide;
+  if (p.big && !p.wide) {
     for (int32_t b = 0; b < n; ++b) {
       int rc = validate(s[b], b);
       if (rc != CG_OK) return rc;
@@ -578,6 +597,11 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   if (p.big) {
     p.layout = kBig;
     p.lds_hop = big_lds(max_orb).total;
+    if (p.wide) {
+      for (int32_t b = 0; b < n; ++b) p.lds_hop = std::max(p.lds_hop, wide_lds(s[b].L, max_orb).total);
+      if (p.lds_hop > lds_cap)
+        return set_err(CG_ENOSPC, "the label-parallel kernel needs %d bytes of LDS (%d available)", p.lds_hop, lds_cap);
+    }
   } else if (p.use_fx64) {
     p.layout = kFx64;
     p.lds_hop = need_fx64;
@@ -653,7 +677,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.sel = off;       off = align_up(off + (bigl ? sizeof(OccSelect) : 0));
     q.mirror2 = off;   off = align_up(off + (bigl ? (size_t)N * 8 : 0));
     q.occ2 = off;      off = align_up(off + (bigl ? (size_t)NW * 4 : 0));
-    q.bar = off;       off = align_up(off + (bigl ? (size_t)kBarWords * 4 : 0));
+    q.bar = off;       off = align_up(off + (bigl ? (size_t)(kBarWords + kWideSlots * kBarLine) * 4 : 0));
     q.end = off;
   }
   p.NC = max_L <= 64 ? 1 : (max_L <= 128 ? 2 : 3);
@@ -702,6 +726,23 @@ BigFn pick_big_uc(int32_t L, int32_t* grid) {
 BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t* grid) {
   if (clock != CG_CLOCK_DET) return U == 1 ? pick_big_uc<1, 1>(L, grid) : pick_big_uc<2, 1>(L, grid);
   return U == 1 ? pick_big_uc<1, 0>(L, grid) : pick_big_uc<2, 0>(L, grid);
+}
+
+// Label-parallel kernel for one sample of side L (a replica per workgroup).
+template <int U, int CLOCK>
+BigFn pick_wide_uc(int32_t L) {
+  switch (L) {
+    case 16: return k_hops_wide<4, U, CLOCK>;
+    case 32: return k_hops_wide<5, U, CLOCK>;
+    case 64: return k_hops_wide<6, U, CLOCK>;
+    case 128: return k_hops_wide<7, U, CLOCK>;
+    default: return nullptr;
+  }
+}
+
+BigFn pick_wide(int32_t L, int32_t U, int32_t clock) {
+  if (clock != CG_CLOCK_DET) return U == 1 ? pick_wide_uc<1, 1>(L) : pick_wide_uc<2, 1>(L);
+  return U == 1 ? pick_wide_uc<1, 0>(L) : pick_wide_uc<2, 0>(L);
 }
 
 // chunks of 1024 U labels: U labels per thread with 16 waves, 2 U with 8
@@ -839,7 +880,8 @@ int launch_hops(cg_ctx* c, int time_mode) {
     for (int32_t b = 0; b < n; ++b) {
       const DevSample* ds = c->d_samples;
       int32_t sb = b;
-      hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, c->stream, c->d_samples, b);
+      if (p.wide) hipLaunchKernelGGL(k_wide_reset, dim3(1), dim3(64), 0, c->stream, c->d_samples, b);
+      else hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, c->stream, c->d_samples, b);
       HIPCHK(hipGetLastError());
       void* args[] = {(void*)&ds, (void*)&sb, (void*)&ra};
       HIPCHK(hipLaunchCooperativeKernel((const void*)c->big[b].first, dim3(c->big[b].second), dim3(1024), args,
@@ -975,7 +1017,14 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     c->big.resize(n);
     for (int32_t b = 0; b < n && e == hipSuccess; ++b) {
       int32_t g = 0;
-      BigFn fn = pick_big(samples[b].L, p.U, p.clock, &g);
+      BigFn fn = nullptr;
+      if (p.wide) {
+        fn = pick_wide(samples[b].L, p.U, p.clock);
+        g = p.spread ? p.spread : ncu;
+        if (fn) e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop);
+      } else {
+        fn = pick_big(samples[b].L, p.U, p.clock, &g);
+      }
       int per_cu = 0;
       if (fn) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 1024, p.lds_hop);
       if (e == hipSuccess && (!fn || (int64_t)per_cu * ncu < g)) {
