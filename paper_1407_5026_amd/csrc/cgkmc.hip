@@ -419,7 +419,6 @@ int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
   p.layout = kCube;
   p.big = false;
   p.U = 1;
-  p.NC = 1;
   int32_t need = 0, need_exact = 0, max_N = 0;
   for (int32_t b = 0; b < n; ++b) {
     std::vector<Rep3> reps;
@@ -435,6 +434,9 @@ int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
   p.lds_hop = need;
   p.lds_exact = need_exact;
   p.max_N = max_N;
+  // sites per thread of the hop kernel: the power of two covering the largest lattice
+  p.NC = 1;
+  while (p.NC * kCubeThreads < max_N) p.NC *= 2;
   size_t off = 0;
   p.sl.resize(n);
   p.states_off = off;
@@ -758,7 +760,15 @@ HopFn pick_fx(int32_t U, int32_t NC, int32_t NW) {
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
               int32_t block) {
-  if (layout == kCube) return k_hops3;
+  if (layout == kCube) {
+    switch (NC) {
+      case 1: return k_hops3<1>;
+      case 2: return k_hops3<2>;
+      case 4: return k_hops3<4>;
+      case 8: return k_hops3<8>;
+      default: return k_hops3<16>;
+    }
+  }
   if (layout == kFx64) return NC == 1 ? k_hops_fx64<64, 1, 0> : k_hops_fx64<128, 1, 0>;
   if (layout == kRaw)
     return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);

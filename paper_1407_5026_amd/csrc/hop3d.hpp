@@ -131,6 +131,12 @@ __global__ void __launch_bounds__(kInitBlock) k_eps3(const DevSample* __restrict
   }
 }
 
+// SPT: sites per thread (a power of two >= ceil(N / 1024) for the batch's largest lattice);
+// thread t owns sites t + 1024 s and keeps their packed coordinates in registers, and for
+// SPT <= 8 also their FP64 energies (each updated energy is written to LDS for the
+// proposals); at SPT = 16 the energies are updated in LDS, which keeps the kernel within its
+// register budget.
+template <int SPT>
 __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restrict__ samples,
                                                        const int32_t* __restrict__ order, RunArgs ra) {
   constexpr uint32_t M = kCubeThreads;
@@ -176,6 +182,26 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
   for (int k = tid; k < S.n_vec; k += kCubeThreads) vec[k] = (uint32_t)S.vec[k];
   if (tid < 16) tag[tid] = ~0u;  // no round carries this tag
   if (tid == 0) *theta_sh = 0u;
+  // owned sites: coordinates x | y << 8 | z << 16 (L <= 24 < 256) and energies
+  constexpr bool kRegE = SPT <= 8;
+  double e[kRegE ? SPT : 1];
+  uint32_t pc[SPT];
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) {
+    const int l = tid + kCubeThreads * s;
+    if (kRegE) e[kRegE ? s : 0] = 0.0;
+    pc[s] = 0u;
+    if (l < N) {
+      int x, y, z;
+      coords3(l, L, magic, x, y, z);
+      if (kRegE) e[kRegE ? s : 0] = ((const double*)S.eps)[l];
+      pc[s] = (uint32_t)x | ((uint32_t)y << 8) | ((uint32_t)z << 16);
+    }
+  }
+  // orbit search: smallest o < n_orb - 1 with w1 < thr[o], else the last orbit, by a
+  // fixed number of bisection steps over the nondecreasing thresholds
+  int steps = 0;
+  while ((1 << steps) < n_orb) ++steps;
   __syncthreads();
 
   const uint32_t k0 = uni(S.seed_lo), k1 = uni(S.seed_hi), sid = uni(S.sample_id);
@@ -196,8 +222,14 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
         uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = sid, c3 = kTagPropose;
         philox10(c0, c1, c2, c3, k0, k1);
         li = (int)(((uint64_t)c0 * (uint64_t)N) >> 32);
-        int o = 0;
-        while (o < n_orb - 1 && c1 >= thr[o]) ++o;
+        int o = 0, hi_o = n_orb - 1;  // the answer lies in [o, hi_o]
+        for (int k = 0; k < steps; ++k) {
+          if (o < hi_o) {
+            const int mid = (o + hi_o) >> 1;
+            if (c1 >= thr[mid]) o = mid + 1;
+            else hi_o = mid;
+          }
+        }
         const uint32_t ob = orb[o];
         const uint32_t member = (uint32_t)(((uint64_t)c3 * (uint64_t)(ob >> 16)) >> 32);
         const uint32_t pv = vec[(ob & 0xffffu) + member];
@@ -287,17 +319,39 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
       }
     }
     logged += logged < log_cap ? 1 : 0;
-    // step 3b on the owned sites
+    // step 3b on the owned sites: eps_l += 1/r_lj - 1/r_li (the table's 1/r(0) is 0); every
+    // lane has read eps_i and eps_j of this round before the barrier that ended it
     {
       int xi, yi, zi, xj, yj, zj;
       coords3(hi, L, magic, xi, yi, zi);
       coords3(hj, L, magic, xj, yj, zj);
-      for (int l = tid; l < N; l += kCubeThreads) {
-        int x, y, z;
-        coords3(l, L, magic, x, y, z);
-        const double a = tab[(fold_l(z - zj, L) * H1 + fold_l(y - yj, L)) * H1 + fold_l(x - xj, L)];
-        const double b = tab[(fold_l(z - zi, L) * H1 + fold_l(y - yi, L)) * H1 + fold_l(x - xi, L)];
-        eps[l] = eps[l] + (a - b);
+      const uint32_t h1 = (uint32_t)H1;
+      // groups of 4 sites, kept apart by scheduling barriers so that the loads of one group
+      // are in flight together without the whole update's loads held in registers
+#pragma unroll
+      for (int s0 = 0; s0 < SPT; s0 += 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int s = s0 + c;
+          const int l = tid + kCubeThreads * s;
+          if (s < SPT && l < N) {
+            const int x = (int)(pc[s] & 255u), y = (int)((pc[s] >> 8) & 255u), z = (int)(pc[s] >> 16);
+            const uint32_t ja =
+                __umul24(__umul24((uint32_t)fold_l(z - zj, L), h1) + (uint32_t)fold_l(y - yj, L), h1) +
+                (uint32_t)fold_l(x - xj, L);
+            const uint32_t ib =
+                __umul24(__umul24((uint32_t)fold_l(z - zi, L), h1) + (uint32_t)fold_l(y - yi, L), h1) +
+                (uint32_t)fold_l(x - xi, L);
+            if (kRegE) {
+              double& es = e[kRegE ? s : 0];
+              es = es + (tab[ja] - tab[ib]);
+              eps[l] = es;
+            } else {
+              eps[l] = eps[l] + (tab[ja] - tab[ib]);
+            }
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
@@ -311,7 +365,11 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
   }
 
   atomicAdd(theta_sh, theta_cnt);
-  for (int k = tid; k < N; k += kCubeThreads) ((double*)S.eps)[k] = eps[k];
+#pragma unroll
+  for (int s = 0; s < SPT; ++s) {
+    const int l = tid + kCubeThreads * s;
+    if (l < N) ((double*)S.eps)[l] = kRegE ? e[kRegE ? s : 0] : eps[l];
+  }
   __syncthreads();
   for (int k = tid; k < S.NW; k += kCubeThreads) S.occ[k] = occ[k];
   if (tid == 0) {
