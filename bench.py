@@ -138,19 +138,22 @@ def run_form(cg, torch, samples, precision, args, hops_per_step):
                 windows=windows, window_hops=per_win * hops_per_step)
 
 
-def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: int = 0) -> dict:
+def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: int = 0, spread: int = 0,
+                  M: int = 0) -> dict:
     """One sample of side L on the whole GPU (FP64 form): the paper's large-lattice setting
     (nu = 1/2, xi = 1, W = 1, E = T/10; hop cutoff rc = 10, 6 at L = 16), warm untimed hops from the random
     start, then `hops` timed hops.  Per hop the update writes the N FP64 energies of the
     proposals' mirror (8 N bytes) and reads two FP64 inverse distances per site from the
     (|dy|, |dx|) table (16 N bytes, cache-resident for L <= 2048).  variant 6: the
-    label-parallel kernel (a replica of the sample per CU, rounds of 256 x 1024 labels)."""
+    label-parallel kernel (a replica of the sample on each of `spread` workgroups, 0 = every CU;
+    rounds of spread x M labels, M = 1024 or 2048 per workgroup)."""
     from workloads import Sample
 
     rc = 10.0 if L >= 32 else 6.0  # the hop cutoff stays below L/2
     s = Sample(L, L * L // 2, 1.0, 1.0, rc, T, T / 10, 7, 0)
     t0 = time.perf_counter()
-    b = cg.Batch([s], cg.make_opts(precision=cg.CG_FP64, variant=variant, max_labels_per_call=1 << 40))
+    b = cg.Batch([s], cg.make_opts(precision=cg.CG_FP64, variant=variant, spread=spread, M=M,
+                                   max_labels_per_call=1 << 40))
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t0
     if warm:
@@ -171,7 +174,7 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: in
     paper = {0.05: {"64": 0.10, "2048": 1.04}, 0.001: {"64": 0.27, "2048": 1.23}}.get(T, {}).get(str(L))
     us = hop_ms * 1e3 / done
     kernel = "k_hops_wide" if variant == 6 else ("k_hops_big" if L > 192 else "per-sample")
-    return {"L": L, "N": L * L, "rc": rc, "T": T, "E": T / 10, "kernel": kernel, "hops": hops, "warmup_hops": warm,
+    return {"L": L, "N": L * L, "rc": rc, "T": T, "E": T / 10, "kernel": kernel, "spread": spread, "M": M or 1024, "hops": hops, "warmup_hops": warm,
             "hops_per_s": hops / dt, "us_per_hop": dt / hops * 1e6, "kernel_us_per_hop": us,
             "kernel_launches": hop_n, "m_bar": m_bar, "rounds_per_hop": rounds,
             "update_bytes_per_hop": 24 * L * L, "update_GBps": 24 * L * L / (us * 1e-6) / 1e9,
@@ -239,6 +242,9 @@ def main() -> int:
     ap.add_argument("--wide-L", type=int, nargs="*", default=[],
                     help="also time one sample of each of these sides (powers of two, 16..128) with the "
                          "label-parallel kernel (variant 6) at --large-T, FP64")
+    ap.add_argument("--wide-spread", type=int, default=0, help="workgroups per sample of the label-parallel "
+                                                                 "kernel (0 = every CU)")
+    ap.add_argument("--wide-M", type=int, default=1024, help="labels per workgroup and round (1024 or 2048)")
     ap.add_argument("--cubic-L", type=int, default=0,
                     help="also time a batch of simple cubic samples of this side (FP64 form)")
     ap.add_argument("--cubic-hops", type=int, default=2048)
@@ -344,7 +350,8 @@ def main() -> int:
         for L in args.wide_L:
             print(f"[bench] label-parallel sample L={L} T={args.large_T}", file=sys.stderr, flush=True)
             out["label_parallel_fp64"].append(
-                large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4, args.large_T, variant=6))
+                large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4, args.large_T, variant=6,
+                              spread=args.wide_spread, M=args.wide_M))
     if args.cubic_L:
         out["cubic_fp64"] = cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps)
     if not args.skip_cpu:
