@@ -1,0 +1,92 @@
+"""The headline workload at its full size, in the launch configuration bench.py times: 256
+samples at L = 128, T = 0.02 (seed 3, sample ids 0..255), M = 8192, 1024-thread workgroups,
+two steps of 4096 hops from the random start; the FP32 form with its FP64 refresh every 4096
+hops, and the FP64 form.  The oracle checks three of the samples hop for hop (FP64: every
+hop; FP32: up to the first near-tie of the FP64 decision) and their energies at sampled
+sites; properties that hold at any size check all 256: every logged hop moves an electron
+to an empty site, the replayed occupation is the final one, the dipole is the sum of the
+logged dx, the clock is s_last / Gamma, and the FP32 drift stays within 1e-5."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import compare_logs, lazy_oracle_of, oracle_of, require_gpu, say
+from workloads import headline
+
+pytestmark = pytest.mark.gpu
+
+STEP, STEPS, M, K = 4096, 2, 8192, 4096
+CHECKED = (0, 131, 255)
+
+
+def _signed_dx(a, c, L):
+    d = (c % L) - (a % L)
+    d = np.where(d > L // 2, d - L, d)
+    return np.where(d < -(L // 2), d + L, d)
+
+
+def _run(cg, precision):
+    samples = headline(256)
+    b = cg.Batch(samples, cg.make_opts(precision=precision, M=M, block=1024, K_refresh=K,
+                                       log_hops=STEP * STEPS))
+    n0 = [b.occupation(k) for k in range(len(samples))]
+    for _ in range(STEPS):
+        b.run_hops(STEP)
+    return samples, b, n0
+
+
+def _check_every_sample(b, samples, n0, gamma):
+    hops = STEP * STEPS
+    for k, s in enumerate(samples):
+        lab, fr, to = b.hop_log(k)
+        assert len(lab) == hops and np.all(np.diff(lab.astype(np.int64)) > 0), k
+        n = n0[k].copy()
+        for a, c in zip(fr.tolist(), to.tolist()):
+            assert n[a] == 1 and n[c] == 0, k
+            n[a], n[c] = 0, 1
+        assert np.array_equal(n, b.occupation(k)), k
+        st = b.stats(k)
+        assert st["hops"] == hops and st["s_last"] == int(lab[-1]), k
+        assert st["P"] == int(_signed_dx(fr, to, s.L).sum()), k
+        assert abs(st["t"] - float(st["s_last"]) / gamma) <= 1e-14 * st["t"], k
+        assert st["status"] == 0, k
+
+
+def _check_sampled_energies(b, k, s, tol):
+    lazy = lazy_oracle_of(s)
+    lazy.set_occ(b.occupation(k))
+    e = b.energies(k)
+    _, fr, to = b.hop_log(k)
+    sites = np.concatenate([np.random.default_rng(k).choice(s.L * s.L, 6, replace=False), fr[-3:], to[-3:]])
+    for l in sites.tolist():
+        assert abs(e[l] - lazy.site_eps(l)) <= tol, (k, l)
+
+
+def test_headline_fp32_full_size():
+    cg = require_gpu()
+    say("headline FP32 form: 256 samples, L=128, 2 x 4096 hops")
+    samples, b, n0 = _run(cg, cg.CG_FP32_REFRESH)
+    gamma = oracle_of(samples[0]).tower()["Gamma"]
+    _check_every_sample(b, samples, n0, gamma)
+    for k in range(len(samples)):
+        st = b.stats(k)
+        assert st["refreshes"] >= STEPS and st["max_drift"] <= 1e-5, k
+    for k in CHECKED:
+        s = samples[k]
+        agree = compare_logs(s, b.hop_log(k), oracle_of(s).run(STEP * STEPS), tol=1e-4)
+        say(f"headline FP32 sample {k}: {agree} hops identical to the oracle")
+        assert agree >= 20
+        _check_sampled_energies(b, k, s, 1e-5)
+
+
+def test_headline_fp64_full_size():
+    cg = require_gpu()
+    say("headline FP64 form: 256 samples, L=128, 2 x 4096 hops")
+    samples, b, n0 = _run(cg, cg.CG_FP64)
+    gamma = oracle_of(samples[0]).tower()["Gamma"]
+    _check_every_sample(b, samples, n0, gamma)
+    for k in CHECKED:
+        s = samples[k]
+        o = oracle_of(s)
+        assert compare_logs(s, b.hop_log(k), o.run(STEP * STEPS)) == STEP * STEPS
+        assert float(np.abs(b.energies(k) - o.eps()).max()) <= 1e-12
+        _check_sampled_energies(b, k, s, 1e-10)
