@@ -90,3 +90,35 @@ def test_headline_fp64_full_size():
         assert compare_logs(s, b.hop_log(k), o.run(STEP * STEPS)) == STEP * STEPS
         assert float(np.abs(b.energies(k) - o.eps()).max()) <= 1e-12
         _check_sampled_energies(b, k, s, 1e-10)
+
+
+def test_fp32_and_fp64_agree_statistically():
+    """Precision parity of the FP32 form: the headline parameters on 32 samples (seed 3,
+    sample ids 0..31), 244 x 4096 ~ 10^6 hops each from the random start in both forms (the
+    FP32 form refreshing every 4096 hops, so its last refresh ends the run).  The two forms
+    follow the same trajectory only up to the first near-tie, then independent ones; over the
+    32 pairs (same disorder and start) the mean paired difference of the final energy per site
+    (Eq. 1, field-free) and of sigma = P / (N E t) lies within 3 standard errors of zero, and
+    every FP32 refresh saw a drift <= 1e-5."""
+    cg = require_gpu()
+    samples = headline(32)
+    N = samples[0].L ** 2
+    res = {}
+    for prec in (cg.CG_FP32_REFRESH, cg.CG_FP64):
+        say(f"precision parity: form {prec}, 32 samples x 999424 hops")
+        b = cg.Batch(samples, cg.make_opts(precision=prec, M=M, block=1024, K_refresh=K))
+        for _ in range(244):
+            b.run_hops(STEP)
+        st = [b.stats(k) for k in range(32)]
+        assert all(s["hops"] == 244 * STEP and s["status"] == 0 for s in st)
+        if prec == cg.CG_FP32_REFRESH:
+            assert max(s["max_drift"] for s in st) <= 1e-5
+            assert min(s["refreshes"] for s in st) >= 244
+        res[prec] = (np.array([s["H0"] / N for s in st]), np.array([b.current(k)[2] for k in range(32)]))
+        b.close()
+    for name, i in (("energy per site", 0), ("sigma", 1)):
+        d = res[cg.CG_FP32_REFRESH][i] - res[cg.CG_FP64][i]
+        se = d.std(ddof=1) / np.sqrt(len(d))
+        say(f"precision parity {name}: FP32 {res[cg.CG_FP32_REFRESH][i].mean():.6g}, FP64 "
+            f"{res[cg.CG_FP64][i].mean():.6g}, paired mean difference {d.mean():.3g} +- {se:.3g}")
+        assert abs(d.mean()) <= 3 * se or (se == 0 and d.mean() == 0)
