@@ -89,6 +89,21 @@ def test_fp64_l64_hop_for_hop():
     _check_run(cg, b, 0, s, oracle_of(s), hops)
 
 
+def test_fp64_l64_million_hops():
+    """The L=64 configuration (rc = 8, T = 0.05, E = 0.01, M = 1024) for 10^6 hops: the FP64
+    kernel executes the oracle's hops, labels and sites hop for hop (the only divergence
+    allowed is a flip at an FP64 near-tie) and ends with its energies, dipole, clock and
+    occupation."""
+    cg = require_gpu()
+    s = fp64_single()[0]
+    hops = 1_000_000
+    b = _batch(cg, [s], precision=cg.CG_FP64, log_hops=hops, M=1024)
+    say(f"FP64 L=64 {hops} hops (the oracle takes about a minute)")
+    b.run_hops(hops)
+    agree = _check_run(cg, b, 0, s, oracle_of(s), hops)
+    say(f"FP64 L=64: {agree} of {hops} hops identical to the oracle")
+
+
 def test_mixed_batch_hop_for_hop():
     """One launch, samples of different L (odd, not multiples of 64), T, E, W, rc."""
     cg = require_gpu()
