@@ -292,16 +292,24 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     int first = U;
     uint32_t pub0 = 0u, pub1 = 0u;
     float pdh = 0.f;
+    // the value words of every undecided label are read at once (an accepted label makes the
+    // lane's later labels moot, but waiting for its decision would add an LDS round trip)
+    uint32_t wis[U], wjs[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      wis[k] = 0u;
+      wjs[k] = 0u;
+      if ((uint32_t)(tid * U + k) >= dpos) {
+        wis[k] = lds_ld<uint32_t>(lb[k].ai);
+        wjs[k] = lds_ld<uint32_t>(lb[k].aj);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const FxLabel& b = lb[k];
       const uint32_t key = (uint32_t)(tid * U + k);
       const bool open = (first == U) & (key >= dpos);  // not yet decided
-      uint32_t wi = 0u, wj = 0u;
-      if (open) {
-        wi = lds_ld<uint32_t>(b.ai);
-        wj = lds_ld<uint32_t>(b.aj);
-      }
+      const uint32_t wi = open ? wis[k] : 0u, wj = open ? wjs[k] : 0u;
       const float de = __uint_as_float(wj) - __uint_as_float(wi);
       const bool th = open & ((wi & ~wj & 1u) != 0u);  // n_i (1 - n_j) from the value words
       const bool acc = th & (de <= b.th);
