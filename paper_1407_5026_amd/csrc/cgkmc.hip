@@ -712,14 +712,17 @@ HopFn pick_db(int32_t U, int32_t NC, bool exact) {
 using BigFn = void (*)(const DevSample*, int32_t, RunArgs);
 
 // Whole-GPU kernel for one sample of side L: workgroups of 1024 threads owning SPT sites per
-// thread, G = L^2 / (1024 SPT) workgroups (16 at L = 128 up to 256 from L = 512).
+// thread, G = L^2 / (1024 SPT) workgroups.  A grid barrier costs more with more workgroups
+// (2.3 us at 64, 3.2 at 128, 5.1 at 256), the update less: measured per hop, L = 512 takes
+// 12.1 / 9.2 / 8.4 us on 256 / 128 / 64 workgroups, L = 1024 16.6 / 12.9 / 13.8 us, and
+// L = 2048 22.0 us on 256 (128 needs more registers than a thread has).
 template <int U, int CLOCK>
 BigFn pick_big_uc(int32_t L, int32_t* grid) {
   switch (L) {
     case 128: *grid = 16; return k_hops_big<7, 1, U, CLOCK>;
     case 256: *grid = 64; return k_hops_big<8, 1, U, CLOCK>;
-    case 512: *grid = 256; return k_hops_big<9, 1, U, CLOCK>;
-    case 1024: *grid = 256; return k_hops_big<10, 4, U, CLOCK>;
+    case 512: *grid = 64; return k_hops_big<9, 4, U, CLOCK>;
+    case 1024: *grid = 128; return k_hops_big<10, 8, U, CLOCK>;
     case 2048: *grid = 256; return k_hops_big<11, 16, U, CLOCK>;
     default: *grid = 0; return nullptr;
   }
