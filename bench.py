@@ -13,6 +13,11 @@ The headline value is accepted hops/s of the FP32-with-FP64-refresh form; the pl
 form is timed on the same samples and reported beside it.  The JSON line also carries the
 LDS roofline of the hop kernel (algorithmic bytes per launch / mean launch time from HIP
 events on the library's stream) and the CPU oracle timed on this host.
+
+Beside the headline (skipped with --no-legs, each guarded so that it cannot cost the
+headline line): one sample of side 256 ... 2048 on the whole GPU at T = 0.05 (the paper's
+large-lattice setting), one L = 64 sample at T = 0.001 with the label-parallel kernel and
+with one workgroup, and a batch of simple cubic samples (L = 16).
 """
 from __future__ import annotations
 
@@ -173,7 +178,12 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: in
     b.close()
     paper = {0.05: {"64": 0.10, "2048": 1.04}, 0.001: {"64": 0.27, "2048": 1.23}}.get(T, {}).get(str(L))
     us = hop_ms * 1e3 / done
-    kernel = "k_hops_wide" if variant == 6 else ("k_hops_big" if L > 192 else "per-sample")
+    if variant == 6:
+        kernel = "k_hops_wide"
+    elif L > 192:
+        kernel = "k_hops_big"
+    else:
+        kernel = "k_hops_fx64 (one workgroup)" if L in (64, 128) else "k_hops (one workgroup)"
     return {"L": L, "N": L * L, "rc": rc, "T": T, "E": T / 10, "kernel": kernel, "spread": spread, "M": M or 1024, "hops": hops, "warmup_hops": warm,
             "hops_per_s": hops / dt, "us_per_hop": dt / hops * 1e6, "kernel_us_per_hop": us,
             "kernel_launches": hop_n, "m_bar": m_bar, "rounds_per_hop": rounds,
@@ -234,19 +244,23 @@ def main() -> int:
     ap.add_argument("--cpu-hops", type=int, default=8192)
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--large-L", type=int, nargs="*", default=[],
-                    help="also time one sample of each of these sides (powers of two, 256..2048) on the "
-                         "whole GPU, FP64")
-    ap.add_argument("--large-hops", type=int, default=2000)
+    # legs beside the headline (single samples on the whole GPU, the cubic lattice); each is
+    # guarded so that it can never cost the headline line
+    ap.add_argument("--no-legs", action="store_true", help="time the headline workload only")
+    ap.add_argument("--large-L", type=int, nargs="*", default=[256, 512, 1024, 2048],
+                    help="time one sample of each of these sides (powers of two, 256..2048) on the "
+                         "whole GPU, FP64, at --large-T")
+    ap.add_argument("--large-hops", type=int, default=8000)
     ap.add_argument("--large-T", type=float, default=0.05)
-    ap.add_argument("--wide-L", type=int, nargs="*", default=[],
-                    help="also time one sample of each of these sides (powers of two, 16..128) with the "
-                         "label-parallel kernel (variant 6) at --large-T, FP64")
-    ap.add_argument("--wide-spread", type=int, default=0, help="workgroups per sample of the label-parallel "
-                                                                 "kernel (0 = every CU)")
-    ap.add_argument("--wide-M", type=int, default=1024, help="labels per workgroup and round (1024 or 2048)")
-    ap.add_argument("--cubic-L", type=int, default=0,
-                    help="also time a batch of simple cubic samples of this side (FP64 form)")
+    ap.add_argument("--wide-L", type=int, nargs="*", default=[64],
+                    help="time one sample of each of these sides (powers of two, 16..128) with the "
+                         "label-parallel kernel (variant 6) and with one workgroup, at --wide-T, FP64")
+    ap.add_argument("--wide-T", type=float, default=0.001)
+    ap.add_argument("--wide-spread", type=int, default=128, help="workgroups per sample of the label-parallel "
+                                                                   "kernel (0 = every CU)")
+    ap.add_argument("--wide-M", type=int, default=2048, help="labels per workgroup and round (1024 or 2048)")
+    ap.add_argument("--cubic-L", type=int, default=16,
+                    help="time a batch of simple cubic samples of this side (FP64 form; 0 = none)")
     ap.add_argument("--cubic-hops", type=int, default=2048)
     ap.add_argument("--cubic-steps", type=int, default=20)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -339,21 +353,32 @@ def main() -> int:
         out["fp64_value"] = r64["hops"] / r64["seconds"]
         out["fp64_window_hops_per_s"] = [round(v) for v in r64["windows"]]
         out["fp64_ms_per_step"] = r64["seconds"] / args.steps * 1e3
-    if args.large_L:
-        out["large_lattice_fp64"] = []
-        for L in args.large_L:
-            print(f"[bench] whole-GPU sample L={L} T={args.large_T}", file=sys.stderr, flush=True)
-            out["large_lattice_fp64"].append(
-                large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4, args.large_T))
-    if args.wide_L:
-        out["label_parallel_fp64"] = []
-        for L in args.wide_L:
-            print(f"[bench] label-parallel sample L={L} T={args.large_T}", file=sys.stderr, flush=True)
-            out["label_parallel_fp64"].append(
-                large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4, args.large_T, variant=6,
-                              spread=args.wide_spread, M=args.wide_M))
-    if args.cubic_L:
-        out["cubic_fp64"] = cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps)
+    def leg(name, fn):
+        print(f"[bench] {name}", file=sys.stderr, flush=True)
+        try:
+            return fn()
+        except Exception as e:  # reported in the line; the headline stands
+            print(f"[bench] {name} failed: {e!r}", file=sys.stderr, flush=True)
+            return {"error": repr(e)}
+
+    if not args.no_legs:
+        if args.large_L:
+            out["large_lattice_fp64"] = [
+                leg(f"whole-GPU sample L={L} T={args.large_T}",
+                    lambda L=L: large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4, args.large_T))
+                for L in args.large_L]
+        if args.wide_L:
+            out["label_parallel_fp64"] = []
+            for L in args.wide_L:
+                for variant in (6, 0):
+                    out["label_parallel_fp64"].append(
+                        leg(f"single sample L={L} T={args.wide_T} variant {variant}",
+                            lambda L=L, v=variant: large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4,
+                                                                 args.wide_T, variant=v, spread=args.wide_spread if v else 0,
+                                                                 M=args.wide_M if v else 0)))
+        if args.cubic_L:
+            out["cubic_fp64"] = leg(f"cubic batch L={args.cubic_L}",
+                                    lambda: cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps))
     if not args.skip_cpu:
         cores = args.cpu_cores or min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(args.warmup * args.hops_per_step, args.cpu_hops, samples[0].seed, cores)
