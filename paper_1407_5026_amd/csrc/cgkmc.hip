@@ -679,7 +679,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.sel = off;       off = align_up(off + (bigl ? sizeof(OccSelect) : 0));
     q.mirror2 = off;   off = align_up(off + (bigl ? (size_t)N * 8 : 0));
     q.occ2 = off;      off = align_up(off + (bigl ? (size_t)NW * 4 : 0));
-    q.bar = off;       off = align_up(off + (bigl ? (size_t)(kBarWords + kWideSlots * kBarLine) * 4 : 0));
+    q.bar = off;       off = align_up(off + (bigl ? (size_t)kWideSyncWords * 4 : 0));
     q.end = off;
   }
   p.NC = max_L <= 64 ? 1 : (max_L <= 128 ? 2 : 3);

@@ -11,15 +11,17 @@
 //     evaluates base + g Mw + 1 ... base + (g + 1) Mw, the labels above the last executed one
 //     (position dpos) being the undecided ones;
 //   * each workgroup finds its lowest accepted label, and one global atomic minimum per
-//     workgroup over the round's slot gives the round's lowest accepted label (the same
-//     for every workgroup after one grid barrier);
+//     workgroup over the round's slot gives the round's lowest accepted label; the last
+//     arriver at the round's grid barrier reads the slot and publishes it in the barrier's
+//     release word, so every workgroup leaves the barrier with the same winner;
 //   * every workgroup then executes that hop on its own replica (draw of the winning label
 //     recomputed from its counter, the energy update of step 3b in LDS), so a hop needs no
 //     data exchange and no second barrier.
 // The labels, streams, decisions and FP64 arithmetic are those of the other kernels, so the
 // hops equal the oracle's for every G.  Four round slots rotate; the slot of round r + 2 is
-// reset by workgroup 0 during round r, after every workgroup has read it for round r - 2
-// (the barrier of round r - 1 orders both).
+// reset by workgroup 0 during round r: round r - 2's barrier was released (after its last
+// arriver read that slot) before workgroup 0 left it, and every minimum of round r + 2
+// follows workgroup 0's release at the barrier of round r + 1.
 #pragma once
 
 #include "hop_big.hpp"
@@ -27,6 +29,50 @@
 namespace cg {
 
 constexpr uint32_t kWideSlots = 4;  // round slots (one 128-byte line each) after the barrier words
+// after the slots: one line holding the 64-bit release word of the round barrier
+constexpr int kWideRel = kBarWords + (int)kWideSlots * kBarLine;
+constexpr int kWideSyncWords = kWideRel + kBarLine;
+
+// The grid barrier of a round, which also hands out the round's winner: the two-level
+// counter tree of grid_barrier, whose last arriver reads the round's slot (every
+// workgroup's minimum is in it, released before its arrival) and stores (n << 32 | slot)
+// as the release word that every workgroup polls, so no workgroup reads the slot itself.
+__device__ __forceinline__ bool round_barrier(uint32_t* bar, uint32_t& n, uint32_t G, uint32_t* ok_sh,
+                                              const uint32_t* slot, uint32_t* win_sh) {
+  __syncthreads();
+  ++n;
+  if (threadIdx.x == 0) {
+    const uint32_t g = blockIdx.x;
+    const uint32_t gsize = (G + 7u - (g & 7u)) / 8u;
+    const uint32_t ngroups = G < 8u ? G : 8u;
+    uint64_t* rel = (uint64_t*)(bar + kWideRel);
+    const uint32_t old =
+        __hip_atomic_fetch_add(bar + (2 + (g & 7u)) * kBarLine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == n * gsize - 1u) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const uint32_t o2 = __hip_atomic_fetch_add(bar + kBarLine, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 == n * ngroups - 1u) {
+        const uint32_t w = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(rel, ((uint64_t)n << 32) | w, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    uint32_t ok = 1u, spins = 0u;
+    uint64_t v = __hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while ((uint32_t)(v >> 32) < n) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins >= kBarrierSpins) {
+        ok = 0u;
+        break;
+      }
+      v = __hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *win_sh = (uint32_t)v;
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  return *ok_sh != 0u;
+}
 
 // LDS of the wide kernel: the large-sample kernel's proposal tables and records, then the
 // replica's FP64 energies and occupation words, and the FP64 (|dy|, |dx|) table when L <= 64.
@@ -87,6 +133,7 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
   uint4* __restrict__ rec = (uint4*)(smem + lo.b.rec);
   double* __restrict__ tclock = (double*)(smem + lo.b.ctrl);
   uint32_t* __restrict__ bar_ok = (uint32_t*)(smem + lo.b.ctrl + 12);
+  uint32_t* __restrict__ win_sh = (uint32_t*)(smem + lo.b.ctrl + 16);
   double* __restrict__ eps = (double*)(smem + lo.eps);
   uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
   const double* __restrict__ tab = kTabLds ? (const double*)(smem + lo.tab) : S.tab64;
@@ -163,12 +210,11 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
           __hip_atomic_fetch_min(slot + (round % kWideSlots) * kBarLine, r.x, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (!grid_barrier(S.bar, bar_n, G, bar_ok)) {
+      if (!round_barrier(S.bar, bar_n, G, bar_ok, slot + (round % kWideSlots) * kBarLine, win_sh)) {
         status = -3;  // CG_EHIP: a workgroup did not arrive
         break;
       }
-      win = uni(__hip_atomic_load(slot + (round % kWideSlots) * kBarLine, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT));
+      win = uni(*win_sh);
       ++round;
       ++rounds;
       evaluated += MC - dpos;
@@ -281,6 +327,7 @@ __global__ void k_wide_reset(const DevSample* __restrict__ samples, int32_t samp
   const DevSample& S = samples[sample];
   if (threadIdx.x < 10) S.bar[threadIdx.x * kBarLine] = 0u;
   if (threadIdx.x < kWideSlots) S.bar[kBarWords + threadIdx.x * kBarLine] = ~0u;
+  if (threadIdx.x == 0) *(uint64_t*)(S.bar + kWideRel) = 0ull;
 }
 
 }  // namespace cg
