@@ -16,8 +16,9 @@ events on the library's stream) and the CPU oracle timed on this host.
 
 Beside the headline (skipped with --no-legs, each guarded so that it cannot cost the
 headline line): one sample of side 256 ... 2048 on the whole GPU at T = 0.05 (the paper's
-large-lattice setting), one L = 64 sample at T = 0.001 with the label-parallel kernel and
-with one workgroup, and a batch of simple cubic samples (L = 16).
+large-lattice setting), one L = 64 sample at T = 0.001 and one simple cubic L = 16 sample at
+T = 0.003 each with the label-parallel kernel and with one workgroup, and a batch of simple
+cubic samples (L = 16).
 """
 from __future__ import annotations
 
@@ -144,7 +145,7 @@ def run_form(cg, torch, samples, precision, args, hops_per_step):
 
 
 def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: int = 0, spread: int = 0,
-                  M: int = 0) -> dict:
+                  M: int = 0, dim: int = 2) -> dict:
     """One sample of side L on the whole GPU (FP64 form): the paper's large-lattice setting
     (nu = 1/2, xi = 1, W = 1, E = T/10; hop cutoff rc = 10, 6 at L = 16), warm untimed hops from the random
     start, then `hops` timed hops.  Per hop the update writes the N FP64 energies of the
@@ -154,8 +155,9 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: in
     rounds of spread x M labels, M = 1024 or 2048 per workgroup)."""
     from workloads import Sample
 
-    rc = 10.0 if L >= 32 else 6.0  # the hop cutoff stays below L/2
-    s = Sample(L, L * L // 2, 1.0, 1.0, rc, T, T / 10, 7, 0)
+    N = L ** 3 if dim == 3 else L * L
+    rc = 4.0 if dim == 3 else (10.0 if L >= 32 else 6.0)  # the hop cutoff stays below L/2
+    s = Sample(L, N // 2, 1.0, 1.0, rc, T, T / 10, 7, 0, dim=dim)
     t0 = time.perf_counter()
     b = cg.Batch([s], cg.make_opts(precision=cg.CG_FP64, variant=variant, spread=spread, M=M,
                                    max_labels_per_call=1 << 40))
@@ -176,18 +178,20 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: in
     m_bar = (st1["s_last"] - st0["s_last"]) / done
     rounds = (st1["rounds"] - st0["rounds"]) / done
     b.close()
-    paper = {0.05: {"64": 0.10, "2048": 1.04}, 0.001: {"64": 0.27, "2048": 1.23}}.get(T, {}).get(str(L))
+    paper = None if dim == 3 else {0.05: {"64": 0.10, "2048": 1.04}, 0.001: {"64": 0.27, "2048": 1.23}}.get(T, {}).get(str(L))
     us = hop_ms * 1e3 / done
-    if variant == 6:
+    if dim == 3:
+        kernel = "k_hops_wide3" if variant == 6 else "k_hops3 (one workgroup)"
+    elif variant == 6:
         kernel = "k_hops_wide"
     elif L > 192:
         kernel = "k_hops_big"
     else:
         kernel = "k_hops_fx64 (one workgroup)" if L in (64, 128) else "k_hops (one workgroup)"
-    return {"L": L, "N": L * L, "rc": rc, "T": T, "E": T / 10, "kernel": kernel, "spread": spread, "M": M or 1024, "hops": hops, "warmup_hops": warm,
+    return {"L": L, "dim": dim, "N": N, "rc": rc, "T": T, "E": T / 10, "kernel": kernel, "spread": spread, "M": M or 1024, "hops": hops, "warmup_hops": warm,
             "hops_per_s": hops / dt, "us_per_hop": dt / hops * 1e6, "kernel_us_per_hop": us,
             "kernel_launches": hop_n, "m_bar": m_bar, "rounds_per_hop": rounds,
-            "update_bytes_per_hop": 24 * L * L, "update_GBps": 24 * L * L / (us * 1e-6) / 1e9,
+            "update_bytes_per_hop": 24 * N, "update_GBps": 24 * N / (us * 1e-6) / 1e9,
             "init_s": init_s, "paper_gpu_ms_per_hop": paper}
 
 
@@ -259,6 +263,10 @@ def main() -> int:
     ap.add_argument("--wide-spread", type=int, default=128, help="workgroups per sample of the label-parallel "
                                                                    "kernel (0 = every CU)")
     ap.add_argument("--wide-M", type=int, default=2048, help="labels per workgroup and round (1024 or 2048)")
+    ap.add_argument("--wide3-L", type=int, nargs="*", default=[16],
+                    help="time one simple cubic sample of each of these sides (<= 24) with the label-parallel "
+                         "kernel and with one workgroup, at --wide3-T, FP64")
+    ap.add_argument("--wide3-T", type=float, default=0.003)
     ap.add_argument("--cubic-L", type=int, default=16,
                     help="time a batch of simple cubic samples of this side (FP64 form; 0 = none)")
     ap.add_argument("--cubic-hops", type=int, default=2048)
@@ -376,6 +384,15 @@ def main() -> int:
                             lambda L=L, v=variant: large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4,
                                                                  args.wide_T, variant=v, spread=args.wide_spread if v else 0,
                                                                  M=args.wide_M if v else 0)))
+        if args.wide3_L:
+            out["label_parallel_cubic_fp64"] = []
+            for L in args.wide3_L:
+                for variant in (6, 0):
+                    out["label_parallel_cubic_fp64"].append(
+                        leg(f"single cubic sample L={L} T={args.wide3_T} variant {variant}",
+                            lambda L=L, v=variant: large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4,
+                                                                 args.wide3_T, variant=v,
+                                                                 spread=args.wide_spread if v else 0, dim=3)))
         if args.cubic_L:
             out["cubic_fp64"] = leg(f"cubic batch L={args.cubic_L}",
                                     lambda: cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps))

@@ -106,7 +106,8 @@ typedef struct cg_run_opts {
                           sample L = 128; deterministic clock; chunks of 1024 labels for
                           any M): energies in registers, value words in LDS, triangle-
                           ordered FP64 table; the same hops as 1;
-                          6 = label-parallel kernel (FP64, L a power of two in [16, 128]):
+                          6 = label-parallel kernel (FP64; square lattices with L a power of
+                          two in [16, 128], or cubic lattices, deterministic clock):
                           one sample at a time on `spread` workgroups, each holding a
                           replica of the sample and evaluating its own 1024 U labels of a
                           round of spread x 1024 U labels; the round's lowest accepted label

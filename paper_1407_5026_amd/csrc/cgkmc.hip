@@ -20,6 +20,7 @@
 #include "hop_fx.hpp"
 #include "hop_fx64.hpp"
 #include "hop_wide.hpp"
+#include "hop_wide3.hpp"
 #include "kernels.hpp"
 #include "layout.hpp"
 #include "observables.hpp"
@@ -252,6 +253,7 @@ struct Plan {
   bool use_db = false, use_fx = false, use_fx64 = false;
   bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
   bool wide = false; // one sample at a time on G workgroups, each with a replica (variant 6)
+  bool coop = false; // hop kernels run as one cooperative launch per sample (big or wide)
   int32_t spread = 0;  // wide: workgroups per sample (0 = one per CU)
   int32_t layout = kFull, real_bytes = 8, lds_hop = 0, lds_exact = 0, lds_dft = 0, max_N = 0, NC = 1;
   bool any_exact_refresh = false, dft16 = false, dft32 = false, exact = false;
@@ -415,9 +417,12 @@ int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
   }
   if (p.precision != CG_FP64) return set_err(CG_EINVAL, "cubic lattices run the FP64 form");
   if (p.clock != CG_CLOCK_DET) return set_err(CG_EINVAL, "cubic lattices use the deterministic clock");
-  if (p.variant != 0 || p.block != 1024) return set_err(CG_EINVAL, "cubic lattices: variant 0, block 1024");
+  if ((p.variant != 0 && p.variant != 6) || p.block != 1024)
+    return set_err(CG_EINVAL, "cubic lattices: variant 0 or 6, block 1024");
   p.layout = kCube;
   p.big = false;
+  p.wide = p.coop = p.variant == 6;
+  if (p.wide && p.use_graph) return set_err(CG_EINVAL, "use_graph is not available with the label-parallel kernel");
   p.U = 1;
   int32_t need = 0, need_exact = 0, max_N = 0;
   for (int32_t b = 0; b < n; ++b) {
@@ -463,7 +468,8 @@ int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
     q.log_label = off; off = align_up(off + (size_t)p.log_cap * 8);
     q.log_from = off;  off = align_up(off + (size_t)p.log_cap * 4);
     q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
-    q.mirror = q.sel = q.mirror2 = q.occ2 = q.bar = off;
+    q.mirror = q.sel = q.mirror2 = q.occ2 = off;
+    q.bar = off;       off = align_up(off + (p.wide ? (size_t)kWideSyncWords * 4 : 0));
     q.end = off;
   }
   plan_tail(s, n, p, off);
@@ -531,6 +537,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     if (p.use_graph) return set_err(CG_EINVAL, "use_graph is not available with the label-parallel kernel");
   }
   p.big = max_L_all > 192 || p.variant == 4 || p.wide;
+  p.coop = p.big;
   if (p.big && !p.wide) {
     for (int32_t b = 0; b < n; ++b) {
       int rc = validate(s[b], b);
@@ -745,6 +752,17 @@ BigFn pick_wide_uc(int32_t L) {
   }
 }
 
+// Label-parallel kernel for cubic samples: SPT sites per thread of the replica update.
+BigFn pick_wide3(int32_t spt) {
+  switch (spt) {
+    case 1: return k_hops_wide3<1>;
+    case 2: return k_hops_wide3<2>;
+    case 4: return k_hops_wide3<4>;
+    case 8: return k_hops_wide3<8>;
+    default: return k_hops_wide3<16>;
+  }
+}
+
 BigFn pick_wide(int32_t L, int32_t U, int32_t clock) {
   if (clock != CG_CLOCK_DET) return U == 1 ? pick_wide_uc<1, 1>(L) : pick_wide_uc<2, 1>(L);
   return U == 1 ? pick_wide_uc<1, 0>(L) : pick_wide_uc<2, 0>(L);
@@ -888,7 +906,7 @@ int launch_hops(cg_ctx* c, int time_mode) {
   int rc = ev_begin(c, c->ev_hop, c->acc_hop_ms, &start);
   if (rc != CG_OK) return rc;
   const int32_t n = (int32_t)c->desc.size();
-  if (p.big) {
+  if (p.coop) {
     // one cooperative launch per sample, each on the whole GPU
     for (int32_t b = 0; b < n; ++b) {
       const DevSample* ds = c->d_samples;
@@ -1023,7 +1041,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   c->d_samples = (DevSample*)(c->arena + p.samples_off);
   c->d_order = (int32_t*)(c->arena + p.order_off);
   c->d_pending = (int32_t*)(c->arena + p.scratch_off);
-  if (p.big) {
+  if (p.coop) {
     int ncu = 0, dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1032,7 +1050,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
       int32_t g = 0;
       BigFn fn = nullptr;
       if (p.wide) {
-        fn = pick_wide(samples[b].L, p.U, p.clock);
+        fn = p.layout == kCube ? pick_wide3(p.NC) : pick_wide(samples[b].L, p.U, p.clock);
         g = p.spread ? p.spread : ncu;
         if (fn) e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop);
       } else {
@@ -1172,7 +1190,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   HIPCHK_C(hipMemcpyAsync(c->d_samples, c->dev.data(), sizeof(DevSample) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK_C(hipMemcpyAsync(c->d_order, p.order.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
 
-  if (!p.big)
+  if (!p.coop)
     HIPCHK_C(hipFuncSetAttribute((const void*)c->hop, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop));
   if (p.layout == kCube) {
     HIPCHK_C(hipFuncSetAttribute((const void*)k_eps3, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_exact));

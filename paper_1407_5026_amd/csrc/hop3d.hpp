@@ -73,6 +73,48 @@ __device__ __forceinline__ void coords3(int l, int L, uint32_t magic, int& x, in
   y = q - z * L;
 }
 
+// Step 1 for one label: site, displacement, target, 1/|d| and acceptance uniform.  The orbit
+// is the smallest o < n_orb - 1 with w1 < thr[o] (else the last), found by `steps` bisection
+// steps over the nondecreasing thresholds; the member is mulhi(w3, size of the orbit).
+struct Cube3Label {
+  int i, j, dx;
+  double r, u;
+};
+__device__ __forceinline__ Cube3Label draw3(uint64_t lab, uint32_t k0, uint32_t k1, uint32_t sid, int L, int N,
+                                            int H1, int n_orb, int steps, uint32_t magic,
+                                            const uint32_t* __restrict__ thr, const uint32_t* __restrict__ orb,
+                                            const uint32_t* __restrict__ vec, const double* __restrict__ tab) {
+  uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = sid, c3 = kTagPropose;
+  philox10(c0, c1, c2, c3, k0, k1);
+  Cube3Label b;
+  b.i = (int)(((uint64_t)c0 * (uint64_t)N) >> 32);
+  int o = 0, hi_o = n_orb - 1;  // the answer lies in [o, hi_o]
+  for (int k = 0; k < steps; ++k) {
+    if (o < hi_o) {
+      const int mid = (o + hi_o) >> 1;
+      if (c1 >= thr[mid]) o = mid + 1;
+      else hi_o = mid;
+    }
+  }
+  const uint32_t ob = orb[o];
+  const uint32_t member = (uint32_t)(((uint64_t)c3 * (uint64_t)(ob >> 16)) >> 32);
+  const uint32_t pv = vec[(ob & 0xffffu) + member];
+  const int dx = unpack10(pv, 0), dy = unpack10(pv, 10), dz = unpack10(pv, 20);
+  int x, y, z;
+  coords3(b.i, L, magic, x, y, z);
+  x += dx;
+  y += dy;
+  z += dz;
+  x = x < 0 ? x + L : (x >= L ? x - L : x);
+  y = y < 0 ? y + L : (y >= L ? y - L : y);
+  z = z < 0 ? z + L : (z >= L ? z - L : z);
+  b.j = (z * L + y) * L + x;
+  b.dx = dx;
+  b.r = tab[(fold_l(dz, L) * H1 + fold_l(dy, L)) * H1 + fold_l(dx, L)];
+  b.u = ((double)c2 + 0.5) * 0x1p-32;
+  return b;
+}
+
 // FP64 energies of L^3 sites from the definition, m in index order (grid: x over blocks
 // of kInitBlock sites, y over samples); per-block partial sums of the energy (Eq. 1 field-free
 // part: n_l phi_l + 1/2 (n_l - nu)(eps_l - phi_l)) and, for a forced recompute (refresh = 1),
@@ -218,32 +260,13 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
     for (;;) {
       if (!cached) {
         // step 1 for label base + 1 + tid
-        const uint64_t lab = base + 1 + (uint64_t)tid;
-        uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = sid, c3 = kTagPropose;
-        philox10(c0, c1, c2, c3, k0, k1);
-        li = (int)(((uint64_t)c0 * (uint64_t)N) >> 32);
-        int o = 0, hi_o = n_orb - 1;  // the answer lies in [o, hi_o]
-        for (int k = 0; k < steps; ++k) {
-          if (o < hi_o) {
-            const int mid = (o + hi_o) >> 1;
-            if (c1 >= thr[mid]) o = mid + 1;
-            else hi_o = mid;
-          }
-        }
-        const uint32_t ob = orb[o];
-        const uint32_t member = (uint32_t)(((uint64_t)c3 * (uint64_t)(ob >> 16)) >> 32);
-        const uint32_t pv = vec[(ob & 0xffffu) + member];
-        const int dx = unpack10(pv, 0), dy = unpack10(pv, 10), dz = unpack10(pv, 20);
-        int x, y, z;
-        coords3(li, L, magic, x, y, z);
-        x += dx; y += dy; z += dz;
-        x = x < 0 ? x + L : (x >= L ? x - L : x);
-        y = y < 0 ? y + L : (y >= L ? y - L : y);
-        z = z < 0 ? z + L : (z >= L ? z - L : z);
-        lj = (z * L + y) * L + x;
-        ldx = dx;
-        lr = tab[(fold_l(dz, L) * H1 + fold_l(dy, L)) * H1 + fold_l(dx, L)];
-        lu = ((double)c2 + 0.5) * 0x1p-32;
+        const Cube3Label d = draw3(base + 1 + (uint64_t)tid, k0, k1, sid, L, N, H1, n_orb, steps, magic, thr, orb,
+                                   vec, tab);
+        li = d.i;
+        lj = d.j;
+        ldx = d.dx;
+        lr = d.r;
+        lu = d.u;
         cached = true;
       }
       // step 2

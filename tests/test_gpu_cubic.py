@@ -83,6 +83,59 @@ def test_cubic_refused_configurations():
                         ([ok, Sample(16, 128, 1.0, 1.0, 6.0, 0.1, 0.01, 1, 0)], dict(precision=cg.CG_FP64)),
                         ([Sample(25, 7812, 1.0, 1.0, 3.0, 0.08, 0.01, 61, 1, dim=3)], dict(precision=cg.CG_FP64)),
                         ([Sample(8, 256, 1.0, 1.0, 4.0, 0.08, 0.01, 61, 1, dim=3)], dict(precision=cg.CG_FP64)),
-                        ([Sample(8, 256, 1.0, 1.0, 3.0, 0.08, 0.01, 61, 1, dim=4)], dict(precision=cg.CG_FP64))):
+                        ([Sample(8, 256, 1.0, 1.0, 3.0, 0.08, 0.01, 61, 1, dim=4)], dict(precision=cg.CG_FP64)),
+                        ([ok], dict(precision=cg.CG_FP64, variant=3)),
+                        ([ok], dict(precision=cg.CG_FP64, variant=6, use_graph=1))):
         with pytest.raises(cg.CgError):
             _batch(cg, samples, **kw)
+
+
+@pytest.mark.parametrize("spread,pieces", [(1, [2500]), (5, [1, 700, 1799]), (0, [3, 2497])])
+def test_cubic_label_parallel_hop_for_hop(spread, pieces):
+    """The cubic label-parallel kernel (variant 6: a replica of each sample per workgroup,
+    rounds of spread x 1024 labels, one sample after another) executes the oracle's hops for
+    every spread, over launches of several sizes, in a batch of L = 6, 8, 11, 16."""
+    cg = require_gpu()
+    samples = _cubes()
+    hops = sum(pieces)
+    say(f"cubic label-parallel spread={spread}: {hops} hops in {len(pieces)} launches")
+    b = _batch(cg, samples, precision=cg.CG_FP64, log_hops=hops, variant=6, spread=spread)
+    for n in pieces:
+        b.run_hops(n)
+    for k, s in enumerate(samples):
+        o = oracle_of(s)
+        ol = o.run(hops)
+        gl = b.hop_log(k)
+        for x, y in zip(gl, ol):
+            assert np.array_equal(x, y), k
+        assert np.array_equal(b.occupation(k), o.occ())
+        assert float(np.abs(b.energies(k) - o.eps()).max()) <= 1e-12
+        st, sc = b.stats(k), o.scalars()
+        assert st["P"] == sc["P"] and st["hops"] == hops and st["s_last"] == sc["s_last"]
+        assert abs(st["t"] - sc["t"]) <= 1e-12 * sc["t"]
+        assert abs(st["H0"] - sc["H0"]) <= 1e-9 * abs(sc["H0"])
+
+
+def test_cubic_label_parallel_low_temperature_and_run_to_time():
+    """At T = 0.01 (thousands of labels per hop) the label-parallel kernel still follows the
+    oracle hop for hop, and run-to-time stops at the oracle's hop."""
+    cg = require_gpu()
+    s = Sample(12, 864, 1.0, 1.0, 3.0, 0.01, 0.001, 67, 0, dim=3)
+    b = _batch(cg, [s], precision=cg.CG_FP64, log_hops=600, variant=6)
+    o = oracle_of(s)
+    b.run_hops(300)
+    ol = o.run(300)
+    for x, y in zip(b.hop_log(0), ol):
+        assert np.array_equal(x, y)
+    t_end = o.scalars()["t"] * 1.5
+    b.run_time(t_end)
+    st = b.stats(0)
+    assert st["t"] >= t_end and st["hops"] > 300
+    # the oracle reaches the same stopping hop: run it hop by hop to the GPU's count
+    o2 = oracle_of(s)
+    o2.run(st["hops"] - 1)
+    assert o2.scalars()["t"] < t_end
+    o2.run(1)
+    sc = o2.scalars()
+    assert sc["t"] >= t_end and sc["s_last"] == st["s_last"]
+    say(f"cubic label-parallel T=0.01: {st['hops']} hops, m_bar = {st['s_last'] / st['hops']:.0f}")
