@@ -17,8 +17,9 @@ events on the library's stream) and the CPU oracle timed on this host.
 Beside the headline (skipped with --no-legs, each guarded so that it cannot cost the
 headline line): one sample of side 256 ... 2048 on the whole GPU at T = 0.05 (the paper's
 large-lattice setting), one L = 64 sample at T = 0.001 and one simple cubic L = 16 sample at
-T = 0.003 each with the label-parallel kernel and with one workgroup, and a batch of simple
-cubic samples (L = 16).
+T = 0.003 each with the label-parallel kernel and with one workgroup, the uneven batch (96
+samples of L = 32 ... 160 run to simulated time 10^3) and a batch of simple cubic samples
+(L = 16).
 """
 from __future__ import annotations
 
@@ -195,6 +196,35 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: in
             "init_s": init_s, "paper_gpu_ms_per_hop": paper}
 
 
+def uneven(cg, torch, n: int, t_end: float) -> dict:
+    """The uneven batch: n samples with L drawn from {32, 48, 64, 96, 128, 160} and per-sample
+    T, E and W (rc = 10), FP32 form with M and the refresh period autotuned, every sample run
+    from the random start to simulated time t_end.  The batch's largest lattice exceeds 128,
+    so the energies stay in the arena; the samples finish at different hop counts."""
+    from workloads import uneven_batch
+
+    samples = uneven_batch(n)
+    opts = cg.autotune(samples, cg.make_opts(precision=cg.CG_FP32_REFRESH))
+    b = cg.Batch(samples, opts)
+    torch.cuda.synchronize()
+    b.kernel_time()
+    t0 = time.perf_counter()
+    b.run_time(t_end)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hop_ms, hop_n, ref_ms, ref_n = b.kernel_time()
+    st = [b.stats(k) for k in range(n)]
+    b.close()
+    hops = sum(x["hops"] for x in st)
+    by_L = {}
+    for s, x in zip(samples, st):
+        by_L.setdefault(s.L, []).append(x["hops"])
+    return {"samples": n, "t_end": t_end, "M": opts.M, "K_refresh": opts.K_refresh, "hops": hops,
+            "seconds": dt, "hops_per_s": hops / dt, "hop_kernel_ms": hop_ms, "hop_launches": hop_n,
+            "refresh_ms": ref_ms, "max_drift": max(x["max_drift"] for x in st),
+            "mean_hops_by_L": {str(L): round(sum(v) / len(v)) for L, v in sorted(by_L.items())}}
+
+
 def cubic(cg, torch, L: int, batch: int, hops: int, steps: int) -> dict:
     """Batch of simple cubic samples (FP64 form; nu = 1/2, W = 1, xi = 1, rc = 4, T = 0.05,
     E = 0.005) from the random start: one untimed step of `hops` hops per sample, then `steps`
@@ -267,6 +297,9 @@ def main() -> int:
                     help="time one simple cubic sample of each of these sides (<= 24) with the label-parallel "
                          "kernel and with one workgroup, at --wide3-T, FP64")
     ap.add_argument("--wide3-T", type=float, default=0.003)
+    ap.add_argument("--uneven", type=int, default=96,
+                    help="time the uneven batch of this many samples to --uneven-t (0 = none)")
+    ap.add_argument("--uneven-t", type=float, default=1000.0)
     ap.add_argument("--cubic-L", type=int, default=16,
                     help="time a batch of simple cubic samples of this side (FP64 form; 0 = none)")
     ap.add_argument("--cubic-hops", type=int, default=2048)
@@ -393,6 +426,9 @@ def main() -> int:
                             lambda L=L, v=variant: large_lattice(cg, torch, L, args.large_hops, args.large_hops // 4,
                                                                  args.wide3_T, variant=v,
                                                                  spread=args.wide_spread if v else 0, dim=3)))
+        if args.uneven:
+            out["uneven_batch_fp32"] = leg(f"uneven batch of {args.uneven} samples to t={args.uneven_t}",
+                                           lambda: uneven(cg, torch, args.uneven, args.uneven_t))
         if args.cubic_L:
             out["cubic_fp64"] = leg(f"cubic batch L={args.cubic_L}",
                                     lambda: cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps))
