@@ -179,6 +179,11 @@ int cg_get_occupation(cg_ctx* ctx, int32_t sample, uint8_t* host_out);
 int cg_get_local_energies(cg_ctx* ctx, int32_t sample, double* host_out);
 int cg_get_phi(cg_ctx* ctx, int32_t sample, double* host_out);
 int cg_get_stats(cg_ctx* ctx, int32_t sample, cg_stats* out);
+/* Simulated clock of one sample (units of the attempt time): the deterministic form
+ * t = s_last / Gamma, or the sum of the drawn increments (section "Hopping conduction in the
+ * Coulomb glass", step 3c).  Synchronizes the context stream; CG_EINVAL for a bad sample
+ * index or a null pointer. */
+int cg_get_clock(cg_ctx* ctx, int32_t sample, double* t);
 /* Clock and current: t, dipole change P and sigma = P / (N E t) (0 if E t == 0). */
 int cg_get_current(cg_ctx* ctx, int32_t sample, double* t, int64_t* P, double* sigma);
 /* Executed-hop log of one sample: labels, origin and destination sites, up to `cap`

@@ -32,7 +32,7 @@ CG_CLOCK_GAMMA = 2
 EXPORTS = (
     "cg_arena_bytes", "cg_create", "cg_destroy", "cg_run_hops", "cg_run_time", "cg_refresh",
     "cg_set_TE", "cg_get_occupation", "cg_get_local_energies", "cg_get_phi", "cg_get_stats",
-    "cg_get_current", "cg_get_hop_log", "cg_take_kernel_time", "cg_autotune", "cg_last_error",
+    "cg_get_clock", "cg_get_current", "cg_get_hop_log", "cg_take_kernel_time", "cg_autotune", "cg_last_error",
     "cg_save", "cg_load", "cg_dos",
 )
 
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     L.cg_get_local_energies.argtypes = [vp, C.c_int32, P(C.c_double)]
     L.cg_get_phi.argtypes = [vp, C.c_int32, P(C.c_double)]
     L.cg_get_stats.argtypes = [vp, C.c_int32, P(cg_stats)]
+    L.cg_get_clock.argtypes = [vp, C.c_int32, P(C.c_double)]
     L.cg_get_current.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_int64), P(C.c_double)]
     L.cg_get_hop_log.argtypes = [vp, C.c_int32, P(C.c_uint64), P(C.c_int32), P(C.c_int32), C.c_int64,
                                  P(C.c_int64)]
@@ -231,6 +232,11 @@ class Batch:
         d = {k: getattr(s, k) for k, _ in cg_stats._fields_}
         d["phase_cycles"] = list(s.phase_cycles)
         return d
+
+    def clock(self, b: int) -> float:
+        t = C.c_double()
+        _check(load().cg_get_clock(self._h, b, C.byref(t)))
+        return t.value
 
     def current(self, b: int):
         t, P, sig = C.c_double(), C.c_int64(), C.c_double()

@@ -1494,6 +1494,15 @@ int cg_get_stats(cg_ctx* c, int32_t b, cg_stats* out) {
   return CG_OK;
 }
 
+int cg_get_clock(cg_ctx* c, int32_t b, double* t) {
+  if (!t) return set_err(CG_EINVAL, "null output");
+  cg_stats s;
+  int rc = cg_get_stats(c, b, &s);
+  if (rc != CG_OK) return rc;
+  *t = s.t;
+  return CG_OK;
+}
+
 int cg_get_current(cg_ctx* c, int32_t b, double* t, int64_t* P, double* sigma) {
   cg_stats s;
   int rc = cg_get_stats(c, b, &s);

@@ -172,6 +172,7 @@ def test_run_time_matches_oracle():
         st, sc = b.stats(0), o.scalars()
         assert st["hops"] == sc["hops"] and st["s_last"] == sc["s_last"]
         assert st["t"] == sc["t"] and st["t"] >= t_end
+        assert b.clock(0) == st["t"] == b.current(0)[0]
     o2 = oracle_of(s)
     compare_logs(s, b.hop_log(0), o2.run(int(b.stats(0)["hops"])))
 
