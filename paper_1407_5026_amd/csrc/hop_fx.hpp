@@ -345,8 +345,10 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
       win2 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, wl);
     }
     ++round;
-    ++rounds;
-    evaluated += M - dpos;
+    if (wid == 0) {  // counters read only at the end, by thread 0
+      ++rounds;
+      evaluated += M - dpos;
+    }
     CG_MARK(tc2)
     if (mk != 0u) break;
     // every label of the chunk is rejected
@@ -372,20 +374,24 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     dpos = key + 1;
     ++hops;
     ++since;
-    P_ += hdx;
-    H0 = H0 + (double)dh0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
-    if (tid == 0) {
-      atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
-      atomicOr(&occ[hj >> 5], 1u << (hj & 31));
-      if (logged < log_cap) {
-        log_label[logged] = q;
-        log_from[logged] = hi;
-        log_to[logged] = hj;
+    // the state written back at the end (by thread 0): kept by wave 0 only, so that the
+    // other waves' scalar work after the barrier is just what their update needs
+    if (wid == 0) {
+      P_ += hdx;
+      H0 = H0 + (double)dh0;
+      sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+      if (tid == 0) {
+        atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
+        atomicOr(&occ[hj >> 5], 1u << (hj & 31));
+        if (logged < log_cap) {
+          log_label[logged] = q;
+          log_from[logged] = hi;
+          log_to[logged] = hj;
+        }
+        if (CLOCK != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
       }
-      if (CLOCK != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
+      logged += logged < log_cap ? 1 : 0;
     }
-    logged += logged < log_cap ? 1 : 0;
     // the owners of i and j move their occupation marks: site (x, y) is slot (y / NW) NC +
     // (x >> 6) of lane x & 63 in wave y % NW; the slot index is wave-uniform, so a short
     // branch tree picks the register

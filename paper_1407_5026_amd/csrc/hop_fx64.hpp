@@ -254,8 +254,10 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
         win3 = (uint32_t)__builtin_amdgcn_readlane((int)rec.w, wl);
       }
       ++round;
-      ++rounds;
-      evaluated += M - dpos;
+      if (wid == 0) {  // counters read only at the end, by thread 0
+        ++rounds;
+        evaluated += M - dpos;
+      }
       if (mk != 0u) break;
       base += M;
       dpos = 0;
@@ -277,20 +279,24 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
     s_last = q;
     dpos = key + 1;
     ++hops;
-    P_ += hdx;
-    H0 = H0 + dh0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
-    if (tid == 0) {
-      atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
-      atomicOr(&occ[hj >> 5], 1u << (hj & 31));
-      if (logged < log_cap) {
-        S.log_label[logged] = q;
-        S.log_from[logged] = hi;
-        S.log_to[logged] = hj;
+    // the state written back at the end (by thread 0): kept by wave 0 only, so that the
+    // other waves' scalar work after the barrier is just what their update needs
+    if (wid == 0) {
+      P_ += hdx;
+      H0 = H0 + dh0;
+      sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+      if (tid == 0) {
+        atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
+        atomicOr(&occ[hj >> 5], 1u << (hj & 31));
+        if (logged < log_cap) {
+          S.log_label[logged] = q;
+          S.log_from[logged] = hi;
+          S.log_to[logged] = hj;
+        }
+        if (CLOCK != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
       }
-      if (CLOCK != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
+      logged += logged < log_cap ? 1 : 0;
     }
-    logged += logged < log_cap ? 1 : 0;
 
     // step 3b on the owned sites: eps += 1/r_lj - 1/r_li from the triangle table.  The
     // column distances are per lane, a row's distance is the same for the whole wave.
