@@ -351,7 +351,7 @@ def main() -> int:
     per_launch_hops = r32["hops"] / max(r32["hop_launches"], 1)
     mean_launch_s = r32["hop_ms"] / max(r32["hop_launches"], 1) * 1e-3
     achieved = bytes_per_hop * per_launch_hops / mean_launch_s / 1e9
-    kernel = f"k_hops_fx<128, {1 if args.M <= 1024 else 2}, {0 if args.clock == 0 else 1}, 16>"
+    kernel = f"k_hops_fx<128, {1 if args.M <= 1024 else 2}, {0 if args.clock == 0 else 1}, 16, false>"
     out = {
         "metric": "accepted hops/s per GPU (L=128, T=0.02, batched) FP32+refresh vs FP64 PR",
         "value": value,

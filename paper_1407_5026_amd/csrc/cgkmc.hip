@@ -769,18 +769,23 @@ BigFn pick_wide(int32_t L, int32_t U, int32_t clock) {
 }
 
 // chunks of 1024 U labels: U labels per thread with 16 waves, 2 U with 8
-template <int CLOCK>
-HopFn pick_fx(int32_t U, int32_t NC, int32_t NW) {
+template <int CLOCK, bool TIM>
+HopFn pick_fx_t(int32_t U, int32_t NC, int32_t NW) {
   if (NW == 8) {
-    if (NC == 1) return U == 1 ? k_hops_fx<64, 2, CLOCK, 8> : k_hops_fx<64, 4, CLOCK, 8>;
-    return U == 1 ? k_hops_fx<128, 2, CLOCK, 8> : k_hops_fx<128, 4, CLOCK, 8>;
+    if (NC == 1) return U == 1 ? k_hops_fx<64, 2, CLOCK, 8, TIM> : k_hops_fx<64, 4, CLOCK, 8, TIM>;
+    return U == 1 ? k_hops_fx<128, 2, CLOCK, 8, TIM> : k_hops_fx<128, 4, CLOCK, 8, TIM>;
   }
-  if (NC == 1) return U == 1 ? k_hops_fx<64, 1, CLOCK, 16> : k_hops_fx<64, 2, CLOCK, 16>;
-  return U == 1 ? k_hops_fx<128, 1, CLOCK, 16> : k_hops_fx<128, 2, CLOCK, 16>;
+  if (NC == 1) return U == 1 ? k_hops_fx<64, 1, CLOCK, 16, TIM> : k_hops_fx<64, 2, CLOCK, 16, TIM>;
+  return U == 1 ? k_hops_fx<128, 1, CLOCK, 16, TIM> : k_hops_fx<128, 2, CLOCK, 16, TIM>;
+}
+
+template <int CLOCK>
+HopFn pick_fx(int32_t U, int32_t NC, int32_t NW, bool timers) {
+  return timers ? pick_fx_t<CLOCK, true>(U, NC, NW) : pick_fx_t<CLOCK, false>(U, NC, NW);
 }
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
-              int32_t block) {
+              int32_t block, bool timers) {
   if (layout == kCube) {
     switch (NC) {
       case 1: return k_hops3<1>;
@@ -792,7 +797,7 @@ HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool ex
   }
   if (layout == kFx64) return NC == 1 ? k_hops_fx64<64, 1, 0> : k_hops_fx64<128, 1, 0>;
   if (layout == kRaw)
-    return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64) : pick_fx<0>(U, NC, block / 64);
+    return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64, timers) : pick_fx<0>(U, NC, block / 64, timers);
   if (db) return pick_db(U, NC, exact);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
@@ -1070,7 +1075,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
       return set_err(CG_EHIP, "whole-GPU kernel set-up: %s", hipGetErrorString(e));
     }
   } else {
-    c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block);
+    c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block, p.timers != 0);
   }
 
   auto fail = [&](int code) {

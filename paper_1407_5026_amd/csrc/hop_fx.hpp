@@ -163,8 +163,10 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C
 }
 
 // CLOCK = 0: deterministic clock t = s_last / Gamma; 1: Gaussian increments (step 3c), the
-// only per-hop call, kept out of the deterministic instance.
-template <int L, int U, int CLOCK, int NW>
+// only per-hop call, kept out of the deterministic instance.  TIM: per-phase shader-cycle
+// timers, compiled only into the instances that run with them (a runtime test of the flag
+// at every phase costs the untimed kernel ~4%).
+template <int L, int U, int CLOCK, int NW, bool TIM>
 __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict__ samples,
                                                   const int32_t* __restrict__ order, RunArgs ra) {
   using G = FxGeo<L, NW>;
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   uint32_t theta_cnt = 0;
   uint32_t round = 0;  // tag of the current evaluation round
   uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
-  const bool timers = ra.timers != 0;
+  constexpr bool timers = TIM;
 #define CG_MARK(acc)                                          \
   if (timers) {                                               \
     const uint64_t now_ = __builtin_amdgcn_s_memtime();       \

@@ -523,3 +523,24 @@ def test_fp64_exact_geometry_kernel(L):
     assert compare_logs(samples[0], b5.hop_log(0), o.run(hops)) == hops
     assert float(np.abs(b5.energies(0) - o.eps()).max()) <= 1e-12
     say(f"FP64 exact-geometry kernel L={L}: {hops} hops equal to the generic kernel and the oracle")
+
+
+def test_phase_timers_do_not_change_the_trajectory():
+    """The FP32 exact-geometry kernel with its phase timers compiled in (phase_timers = 1, a
+    separate kernel instance) executes the same hops and energies bit for bit as the untimed
+    instance, and only the timed one reports cycles."""
+    cg = require_gpu()
+    from workloads import headline
+
+    samples = headline(2, seed=31)
+    hops = 2000
+    a = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, K_refresh=1024, log_hops=hops)
+    b = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, K_refresh=1024, log_hops=hops, phase_timers=1)
+    a.run_hops(hops)
+    b.run_hops(hops)
+    for k in range(len(samples)):
+        for x, y in zip(a.hop_log(k), b.hop_log(k)):
+            assert np.array_equal(x, y)
+        assert np.array_equal(a.energies(k), b.energies(k))
+        assert all(c > 0 for c in b.stats(k)["phase_cycles"][1:])
+        assert all(c == 0 for c in a.stats(k)["phase_cycles"])
