@@ -336,9 +336,10 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     }
     CG_MARK(tc1)
     __syncthreads();
-    uint4 rec = make_uint4(0u, 0u, 0u, ~round);
-    if (lane < kMaxWaves) rec = info[lane];
-    const unsigned long long won = __ballot(rec.w == round);
+    // every lane reads a record (lanes l and l + 16 k share one: broadcast reads), only the
+    // first 16 lanes vote
+    const uint4 rec = info[lane & (kMaxWaves - 1)];
+    const unsigned long long won = __ballot(rec.w == round) & ((1ull << kMaxWaves) - 1ull);
     mk = won != 0ull ? 1u : 0u;
     if (won != 0ull) {
       const int wl = __ffsll(won) - 1;
