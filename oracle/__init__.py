@@ -12,6 +12,7 @@ Metropolis acceptance, step 3b's local-energy update and step 3c's clock.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -51,66 +52,102 @@ class _Scalars(C.Structure):
 _lib = None
 
 
+def _bind(path: str):
+    """Load a build of the oracle sources and declare the signatures of its functions."""
+    L = C.CDLL(path)
+    P = C.POINTER
+    L.or_philox.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+    L.or_create.argtypes = [P(_Params), P(C.c_void_p)]
+    L.or_create.restype = C.c_int
+    L.or_create_lazy.argtypes = [P(_Params), P(C.c_void_p)]
+    L.or_create_lazy.restype = C.c_int
+    L.or_site_eps.argtypes = [C.c_void_p, C.c_int32]
+    L.or_site_eps.restype = C.c_double
+    L.or_destroy.argtypes = [C.c_void_p]
+    L.or_dims.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+    L.or_tower.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_int32), P(C.c_int32),
+                           P(C.c_int32), P(C.c_int32), P(C.c_double), P(C.c_double)]
+    L.or_draw.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int32), P(C.c_double)]
+    L.or_vec_prob.argtypes = [C.c_void_p, C.c_int32]
+    L.or_vec_prob.restype = C.c_double
+    L.or_invr.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    L.or_invr.restype = C.c_double
+    for f in ("or_get_phi", "or_get_eps"):
+        getattr(L, f).argtypes = [C.c_void_p, P(C.c_double)]
+    L.or_get_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
+    L.or_get_scalars.argtypes = [C.c_void_p, P(_Scalars)]
+    L.or_set_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
+    L.or_set_occ.restype = C.c_int
+    L.or_run.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int64, P(C.c_uint64),
+                         P(C.c_int32), P(C.c_int32), C.c_int64]
+    L.or_run.restype = C.c_int64
+    L.or_recompute_eps.argtypes = [C.c_void_p, P(C.c_double)]
+    L.or_energy.argtypes = [C.c_void_p]
+    L.or_energy.restype = C.c_double
+    L.or_move.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
+    L.or_move.restype = C.c_double
+    L.or_acceptance.argtypes = [C.c_void_p]
+    L.or_acceptance.restype = C.c_double
+    L.or_naive_run.argtypes = [C.c_void_p, C.c_double]
+    L.or_naive_run.restype = C.c_int64
+    L.or3_create.argtypes = [P(_Params), P(C.c_void_p)]
+    L.or3_create.restype = C.c_int
+    L.or3_destroy.argtypes = [C.c_void_p]
+    L.or3_draw.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int32), P(C.c_double)]
+    L.or3_invr.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    L.or3_invr.restype = C.c_double
+    L.or3_run.argtypes = [C.c_void_p, C.c_int64, P(C.c_uint64), P(C.c_int32), P(C.c_int32), C.c_int64]
+    L.or3_run.restype = C.c_int64
+    L.or3_energy.argtypes = [C.c_void_p]
+    L.or3_energy.restype = C.c_double
+    L.or3_get.argtypes = [C.c_void_p, P(C.c_uint8), P(C.c_double), P(C.c_double)]
+    L.or3_scalars.argtypes = [C.c_void_p, P(_Scalars)]
+    L.or3_tower.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_uint64), P(C.c_int32),
+                            P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+    L.or3_set_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
+    L.or_gamma_dt.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_double]
+    L.or_gamma_dt.restype = C.c_double
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
-        path = build(force=False)
-        L = C.CDLL(path)
-        P = C.POINTER
-        L.or_philox.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
-        L.or_create.argtypes = [P(_Params), P(C.c_void_p)]
-        L.or_create.restype = C.c_int
-        L.or_create_lazy.argtypes = [P(_Params), P(C.c_void_p)]
-        L.or_create_lazy.restype = C.c_int
-        L.or_site_eps.argtypes = [C.c_void_p, C.c_int32]
-        L.or_site_eps.restype = C.c_double
-        L.or_destroy.argtypes = [C.c_void_p]
-        L.or_dims.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
-        L.or_tower.argtypes = [C.c_void_p, P(C.c_uint64), P(C.c_int32), P(C.c_int32),
-                               P(C.c_int32), P(C.c_int32), P(C.c_double), P(C.c_double)]
-        L.or_draw.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int32), P(C.c_double)]
-        L.or_vec_prob.argtypes = [C.c_void_p, C.c_int32]
-        L.or_vec_prob.restype = C.c_double
-        L.or_invr.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
-        L.or_invr.restype = C.c_double
-        for f in ("or_get_phi", "or_get_eps"):
-            getattr(L, f).argtypes = [C.c_void_p, P(C.c_double)]
-        L.or_get_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
-        L.or_get_scalars.argtypes = [C.c_void_p, P(_Scalars)]
-        L.or_set_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
-        L.or_set_occ.restype = C.c_int
-        L.or_run.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int64, P(C.c_uint64),
-                             P(C.c_int32), P(C.c_int32), C.c_int64]
-        L.or_run.restype = C.c_int64
-        L.or_recompute_eps.argtypes = [C.c_void_p, P(C.c_double)]
-        L.or_energy.argtypes = [C.c_void_p]
-        L.or_energy.restype = C.c_double
-        L.or_move.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
-        L.or_move.restype = C.c_double
-        L.or_acceptance.argtypes = [C.c_void_p]
-        L.or_acceptance.restype = C.c_double
-        L.or_set_mutation.argtypes = [C.c_int32]
-        L.or_naive_run.argtypes = [C.c_void_p, C.c_double]
-        L.or_naive_run.restype = C.c_int64
-        L.or3_create.argtypes = [P(_Params), P(C.c_void_p)]
-        L.or3_create.restype = C.c_int
-        L.or3_destroy.argtypes = [C.c_void_p]
-        L.or3_draw.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int32), P(C.c_double)]
-        L.or3_invr.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
-        L.or3_invr.restype = C.c_double
-        L.or3_run.argtypes = [C.c_void_p, C.c_int64, P(C.c_uint64), P(C.c_int32), P(C.c_int32), C.c_int64]
-        L.or3_run.restype = C.c_int64
-        L.or3_energy.argtypes = [C.c_void_p]
-        L.or3_energy.restype = C.c_double
-        L.or3_get.argtypes = [C.c_void_p, P(C.c_uint8), P(C.c_double), P(C.c_double)]
-        L.or3_scalars.argtypes = [C.c_void_p, P(_Scalars)]
-        L.or3_tower.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_uint64), P(C.c_int32),
-                                P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]
-        L.or3_set_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
-        L.or_gamma_dt.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_double]
-        L.or_gamma_dt.restype = C.c_double
-        _lib = L
+        _lib = _bind(build(force=False))
     return _lib
+
+
+@contextlib.contextmanager
+def using_build(path: str):
+    """Run the wrappers against another build of the oracle sources (the mutation tests build
+    copies with a planted mistake); the regular build is restored on exit."""
+    global _lib
+    saved = lib()
+    _lib = _bind(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def build_copy(source_text: str, out_dir: str) -> str:
+    """Compile a modified copy of oracle.c (plus oracle3d.c) with the regular flags into
+    out_dir; returns the library path."""
+    import shutil
+
+    for f in ("oracle.h", "oracle3d.c"):
+        shutil.copy(os.path.join(_HERE, f), os.path.join(out_dir, f))
+    src = os.path.join(out_dir, "oracle.c")
+    with open(src, "w") as fh:
+        fh.write(source_text)
+    out = os.path.join(out_dir, "liboracle_copy.so")
+    subprocess.run(["gcc", *CFLAGS, "-o", out, src, os.path.join(out_dir, "oracle3d.c"), "-lm"], check=True)
+    return out
+
+
+def source() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
 
 
 def _ptr(a, ctype):
@@ -129,11 +166,6 @@ def philox(ctr, key) -> np.ndarray:
 def gamma_dt(seed: int, sample_id: int, hop: int, m: int, Gamma: float) -> float:
     """The exact serial clock's increment for hop `hop` after m proposals (Gamma(m, Gamma))."""
     return lib().or_gamma_dt(seed, sample_id, hop, m, Gamma)
-
-
-def set_mutation(m: int) -> None:
-    """Plant a known mistake in the oracle (0 restores it); used to show the pins catch it."""
-    lib().or_set_mutation(int(m))
 
 
 class Oracle:

@@ -13,9 +13,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-static int32_t g_mutation = 0;
-void or_set_mutation(int32_t m) { g_mutation = m; }
-
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based RNG the
  * paper uses for its many parallel streams (section "Hopping conduction",
@@ -181,8 +178,7 @@ static int build_tower(or_state* st) {
       ++nv;
     }
     double r = sqrt((double)reps[o].r2);
-    double w = (g_mutation == 6) ? (double)nu * exp(-1.0 * r / xi)
-                                 : (double)nu * exp(-2.0 * r / xi);
+    double w = (double)nu * exp(-2.0 * r / xi);
     acc = acc + w;
     cum[o] = acc;
   }
@@ -204,7 +200,7 @@ void or_draw(const or_state* st, uint64_t s, int32_t* i, int32_t* v, double* u) 
   *i = (int32_t)(((uint64_t)w[0] * (uint64_t)st->N) >> 32);
   int32_t o = 0;
   while (!((uint64_t)w[1] < st->thr[o])) ++o;
-  uint32_t member = (g_mutation == 5) ? 0u : (w[3] & (uint32_t)(st->orb_size[o] - 1));
+  uint32_t member = w[3] & (uint32_t)(st->orb_size[o] - 1);
   *v = st->orb_first[o] + (int32_t)member;
   *u = unit52(w[2], w[3]);
 }
@@ -221,13 +217,20 @@ double or_vec_prob(const or_state* st, int32_t v) {
 /* eps_l = phi_l + sum_{m != l} (n_m - nu) / r_lm, summed over m = 0..N-1 in order
  * (definition of the single-particle energies after Eq. 2).                     */
 static double site_eps(const or_state* st, int32_t l) {
-  const int32_t L = st->p.L, N = st->N;
+  const int32_t L = st->p.L;
   int32_t xl = l % L, yl = l / L;
   double acc = st->phi[l];
-  for (int32_t m = 0; m < N; ++m) {
-    if (m == l) continue;
-    double q = (g_mutation == 7) ? (double)st->n[m] : (double)st->n[m] - st->nu;
-    acc = acc + q * or_invr(st, xl - m % L, yl - m / L);
+  /* m = ym L + xm runs over 0..N-1 in index order */
+  for (int32_t ym = 0; ym < L; ++ym) {
+    const double* row = st->invr + (size_t)wrap(yl - ym, L) * (size_t)L;
+    for (int32_t xm = 0; xm < L; ++xm) {
+      int32_t m = ym * L + xm;
+      if (m == l) continue;
+      int32_t ddx = xl - xm;
+      if (ddx < 0) ddx += L;
+      double q = (double)st->n[m] - st->nu;
+      acc = acc + q * row[ddx];
+    }
   }
   return acc;
 }
@@ -250,10 +253,18 @@ double or_energy(const or_state* st) {
   for (int32_t i = 0; i < N; ++i) h1 = h1 + st->phi[i] * (double)st->n[i];
   for (int32_t i = 0; i < N; ++i) {
     double qi = (double)st->n[i] - st->nu;
-    for (int32_t j = 0; j < N; ++j) {
-      if (j == i) continue;
-      double qj = (double)st->n[j] - st->nu;
-      h2 = h2 + qi * qj * or_invr(st, i % L - j % L, i / L - j / L);
+    int32_t xi = i % L, yi = i / L;
+    /* j = yj L + xj runs over 0..N-1 in index order */
+    for (int32_t yj = 0; yj < L; ++yj) {
+      const double* row = st->invr + (size_t)wrap(yi - yj, L) * (size_t)L;
+      for (int32_t xj = 0; xj < L; ++xj) {
+        int32_t j = yj * L + xj;
+        if (j == i) continue;
+        int32_t ddx = xi - xj;
+        if (ddx < 0) ddx += L;
+        double qj = (double)st->n[j] - st->nu;
+        h2 = h2 + qi * qj * row[ddx];
+      }
     }
   }
   return h1 + 0.5 * h2;
@@ -391,8 +402,6 @@ int or_set_occ(or_state* st, const uint8_t* n) {
 static double delta_h(const or_state* st, int32_t i, int32_t j, int32_t v) {
   double vij = or_invr(st, st->vec_dx[v], st->vec_dy[v]);
   double dx = (double)st->vec_dx[v];
-  if (g_mutation == 1) return ((st->eps[j] - st->eps[i]) - vij) + st->p.E * dx;
-  if (g_mutation == 2) return (st->eps[j] - st->eps[i]) - st->p.E * dx;
   return ((st->eps[j] - st->eps[i]) - vij) - st->p.E * dx;
 }
 
@@ -407,7 +416,6 @@ static int32_t partner(const or_state* st, int32_t i, int32_t v) {
  * theta_ij = n_i (1 - n_j) (Eq. 2 and the factorisation that follows it).      */
 static double metropolis(const or_state* st, double dH) {
   if (dH <= 0.0) return 1.0;
-  if (g_mutation == 8) return exp(-dH * st->p.T);
   return exp(-dH / st->p.T);
 }
 
@@ -445,10 +453,8 @@ static void update_eps(or_state* st, int32_t i, int32_t j) {
   for (int32_t y = 0; y < L; ++y)
     for (int32_t x = 0; x < L; ++x) {
       int32_t l = y * L + x;
-      if (g_mutation == 3 && (l == i || l == j)) continue;
       double a = or_invr(st, x - xj, y - yj), b = or_invr(st, x - xi, y - yi);
-      if (g_mutation == 10) st->eps[l] = st->eps[l] + (b - a);
-      else st->eps[l] = st->eps[l] + (a - b);
+      st->eps[l] = st->eps[l] + (a - b);
     }
 }
 
@@ -569,11 +575,7 @@ int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
     or_draw(st, s, &i, &v, &u);
     int32_t j = partner(st, i, v);
     /* step 2: accept with theta_ij min(1, exp(-dH/T)) */
-    if (g_mutation == 4) {
-      if (st->n[i] != 1) continue;
-    } else if (!(st->n[i] == 1 && st->n[j] == 0)) {
-      continue;
-    }
+    if (!(st->n[i] == 1 && st->n[j] == 0)) continue;
     st->theta_pass++;
     double dH = delta_h(st, i, j, v);
     if (!(dH <= 0.0 || u < metropolis(st, dH))) continue;
@@ -581,8 +583,7 @@ int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
     double dH0 = (st->eps[j] - st->eps[i]) - or_invr(st, st->vec_dx[v], st->vec_dy[v]);
     st->n[i] = 0;
     st->n[j] = 1;
-    if (g_mutation == 9) st->P -= st->vec_dx[v];
-    else st->P += st->vec_dx[v];
+    st->P += st->vec_dx[v];
     st->H0 = st->H0 + dH0;
     uint64_t m = s - st->s_last;
     st->s_last = s;

@@ -148,9 +148,6 @@ void or3_tower(const or3_state* st, int32_t* n_orb, int32_t* n_vec, uint64_t* th
                int32_t* size, int32_t* vx, int32_t* vy, int32_t* vz);
 void or3_set_occ(or3_state* st, const uint8_t* n);
 
-/* Planted mistakes for checking that the tests detect them (0 = none). */
-void or_set_mutation(int32_t m);
-
 #ifdef __cplusplus
 }
 #endif

@@ -19,4 +19,3 @@ def _oracle_built():
 
     oracle.build(force=False)
     yield
-    oracle.set_mutation(0)

@@ -1,5 +1,9 @@
-"""Plant known mistakes in the oracle (on the CPU) and show that its pins catch each one."""
-import math
+"""Plant known mistakes in copies of the oracle's source (on the CPU) and show that its pins
+catch each one.  The shipped oracle.c carries no switch: each case below replaces one exact
+piece of its source text, compiles the copy with the regular flags and runs the checks
+against it.  A case whose text no longer occurs in oracle.c fails, so the cases follow the
+source."""
+import tempfile
 
 import pytest
 
@@ -37,40 +41,80 @@ def _gamma():
     return pins.check_gamma_pairs(o, 16, 1.0, 6.0)
 
 
-# mutation id -> (what it plants, checks expected to catch it)
+# case -> (what it plants, (original text, planted text), checks expected to catch it)
 CASES = {
-    1: ("field term sign flipped in dH", [_dh_field]),
-    2: ("-1/r_ij dropped from dH", [_dh_field, pins.check_boltzmann_exact_3x3]),
-    3: ("hop sites skipped by the energy update", [_incremental]),
-    4: ("occupancy filter ignores n_j", [_invariants]),
-    5: ("orbit member always the first", [_draws, pins.check_boltzmann_exact_3x3]),
-    6: ("tunnelling weight exp(-r/xi)", [_gamma, _draws]),
-    7: ("background nu dropped from eps", [pins.check_eps_closed_form_3x3]),
-    8: ("Metropolis uses exp(-dH*T)", [pins.check_boltzmann_exact_3x3]),
-    9: ("dipole sign flipped", [_invariants]),
-    10: ("energy update sign flipped", [_incremental]),
+    1: ("field term sign flipped in dH",
+        ("return ((st->eps[j] - st->eps[i]) - vij) - st->p.E * dx;",
+         "return ((st->eps[j] - st->eps[i]) - vij) + st->p.E * dx;"),
+        [_dh_field]),
+    2: ("-1/r_ij dropped from dH",
+        ("return ((st->eps[j] - st->eps[i]) - vij) - st->p.E * dx;",
+         "return (st->eps[j] - st->eps[i]) - st->p.E * dx;"),
+        [_dh_field, pins.check_boltzmann_exact_3x3]),
+    3: ("hop sites skipped by the energy update",
+        ("      st->eps[l] = st->eps[l] + (a - b);",
+         "      if (l != i && l != j) st->eps[l] = st->eps[l] + (a - b);"),
+        [_incremental]),
+    4: ("occupancy filter ignores n_j",
+        ("    if (!(st->n[i] == 1 && st->n[j] == 0)) continue;\n    st->theta_pass++;",
+         "    if (!(st->n[i] == 1)) continue;\n    st->theta_pass++;"),
+        [_invariants]),
+    5: ("orbit member always the first",
+        ("  uint32_t member = w[3] & (uint32_t)(st->orb_size[o] - 1);",
+         "  uint32_t member = 0u;"),
+        [_draws, pins.check_boltzmann_exact_3x3]),
+    6: ("tunnelling weight exp(-r/xi)",
+        ("    double w = (double)nu * exp(-2.0 * r / xi);",
+         "    double w = (double)nu * exp(-1.0 * r / xi);"),
+        [_gamma, _draws]),
+    7: ("background nu dropped from eps",
+        ("      double q = (double)st->n[m] - st->nu;",
+         "      double q = (double)st->n[m];"),
+        [pins.check_eps_closed_form_3x3]),
+    8: ("Metropolis uses exp(-dH*T)",
+        ("  return exp(-dH / st->p.T);",
+         "  return exp(-dH * st->p.T);"),
+        [pins.check_boltzmann_exact_3x3]),
+    9: ("dipole sign flipped",
+        ("    st->P += st->vec_dx[v];",
+         "    st->P -= st->vec_dx[v];"),
+        [_invariants]),
+    10: ("energy update sign flipped",
+         ("      st->eps[l] = st->eps[l] + (a - b);",
+          "      st->eps[l] = st->eps[l] + (b - a);"),
+         [_incremental]),
 }
 
 
-@pytest.mark.parametrize("mut", sorted(CASES))
-def test_planted_mistake_is_caught(mut):
-    what, checks = CASES[mut]
-    oracle.set_mutation(mut)
-    try:
-        results = []
-        for chk in checks:
-            try:
-                ok, msg = chk()
-            except Exception as e:  # a crash of the check also counts as detection
-                ok, msg = False, f"raised {type(e).__name__}: {e}"
-            results.append((chk.__name__, ok, msg))
-    finally:
-        oracle.set_mutation(0)
-    assert any(not ok for _, ok, _ in results), f"mutation {mut} ({what}) not caught: {results}"
+def _planted(case: int) -> str:
+    _, (old, new), _ = CASES[case]
+    src = oracle.source()
+    assert src.count(old) == 1, f"case {case}: the text it replaces occurs {src.count(old)} times in oracle.c"
+    return src.replace(old, new)
 
 
-def test_unmutated_oracle_passes_the_same_checks():
-    for _, checks in CASES.values():
-        for chk in checks:
-            ok, msg = chk()
-            assert ok, (chk.__name__, msg)
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_planted_mistake_is_caught(case):
+    what, _, checks = CASES[case]
+    with tempfile.TemporaryDirectory() as d:
+        path = oracle.build_copy(_planted(case), d)
+        with oracle.using_build(path):
+            results = []
+            for chk in checks:
+                try:
+                    ok, msg = chk()
+                except Exception as e:  # a crash of the check also counts as detection
+                    ok, msg = False, f"raised {type(e).__name__}: {e}"
+                results.append((chk.__name__, ok, msg))
+    assert any(not ok for _, ok, _ in results), f"case {case} ({what}) not caught: {results}"
+
+
+def test_unmodified_copy_passes_the_same_checks():
+    """The copy mechanism itself plants nothing: an unmodified copy passes every check."""
+    with tempfile.TemporaryDirectory() as d:
+        path = oracle.build_copy(oracle.source(), d)
+        with oracle.using_build(path):
+            for _, _, checks in CASES.values():
+                for chk in checks:
+                    ok, msg = chk()
+                    assert ok, (chk.__name__, msg)
