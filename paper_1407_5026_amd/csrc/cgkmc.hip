@@ -476,6 +476,9 @@ int plan_cube(const cg_sample_desc* s, int32_t n, Plan& p, int32_t lds_cap) {
   return CG_OK;
 }
 
+using BigFn = void (*)(const DevSample*, int32_t, RunArgs);
+BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t spread, int32_t* grid);
+
 int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p, bool query_lds) {
   if (!s || n < 1 || n > 65535) return set_err(CG_EINVAL, "need 1..65535 samples (got %d)", n);
   cg_run_opts def{};
@@ -499,8 +502,9 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   p.use_graph = o->use_graph;
   if (o->variant < 0 || o->variant > 6) return set_err(CG_EINVAL, "variant=%d", o->variant);
   p.variant = o->variant;
-  if (o->spread < 0 || (o->spread != 0 && p.variant != 6))
-    return set_err(CG_EINVAL, "spread=%d (workgroups per sample of variant 6, or 0)", o->spread);
+  if (o->spread < 0 || (o->spread != 0 && p.variant != 0 && p.variant != 4 && p.variant != 6))
+    return set_err(CG_EINVAL, "spread=%d (workgroups per sample of the label-parallel or whole-GPU kernel, or 0)",
+                   o->spread);
   p.spread = o->spread;
   p.K = o->K_refresh ? o->K_refresh : 4096;
   if (p.K < 1) return set_err(CG_EINVAL, "K_refresh=%d", o->K_refresh);
@@ -548,6 +552,14 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     }
     if (p.precision != CG_FP64) return set_err(CG_EINVAL, "the whole-GPU kernel (L > 192 or variant 4) runs the FP64 form");
     if (p.use_graph) return set_err(CG_EINVAL, "use_graph is not available with the whole-GPU kernel");
+    for (int32_t b = 0; b < n && p.spread != 0; ++b) {
+      int32_t g = 0;
+      if (!pick_big(s[b].L, 1, CG_CLOCK_DET, p.spread, &g))
+        return set_err(CG_EINVAL, "sample %d: L=%d has no whole-GPU kernel on %d workgroups", b, s[b].L, p.spread);
+    }
+  } else if (p.spread != 0 && !p.wide) {
+    return set_err(CG_EINVAL, "spread=%d: only the label-parallel and whole-GPU kernels take a workgroup count",
+                   p.spread);
   }
   int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
   for (int32_t b = 0; b < n && !p.big; ++b) {
@@ -716,28 +728,42 @@ HopFn pick_db(int32_t U, int32_t NC, bool exact) {
   return exact ? k_hops_db<2, 2, 8, true> : k_hops_db<2, 2, 8, false>;
 }
 
-using BigFn = void (*)(const DevSample*, int32_t, RunArgs);
-
 // Whole-GPU kernel for one sample of side L: workgroups of 1024 threads owning SPT sites per
 // thread, G = L^2 / (1024 SPT) workgroups.  A grid barrier costs more with more workgroups
 // (2.3 us at 64, 3.2 at 128, 5.1 at 256), the update less: measured per hop, L = 512 takes
 // 12.1 / 9.2 / 8.4 us on 256 / 128 / 64 workgroups, L = 1024 16.6 / 12.9 / 13.8 us, and
 // L = 2048 22.0 us on 256 (128 needs more registers than a thread has).
+// `spread` (0 = the size's default) may also select L = 256 on 16 workgroups (four sites per
+// thread), the same kernel with several sites per thread at a size the full oracle can check.
 template <int U, int CLOCK>
-BigFn pick_big_uc(int32_t L, int32_t* grid) {
+BigFn pick_big_uc(int32_t L, int32_t spread, int32_t* grid) {
+  *grid = 0;
+  BigFn fn = nullptr;
+  int32_t g = 0;
   switch (L) {
-    case 128: *grid = 16; return k_hops_big<7, 1, U, CLOCK>;
-    case 256: *grid = 64; return k_hops_big<8, 1, U, CLOCK>;
-    case 512: *grid = 64; return k_hops_big<9, 4, U, CLOCK>;
-    case 1024: *grid = 128; return k_hops_big<10, 8, U, CLOCK>;
-    case 2048: *grid = 256; return k_hops_big<11, 16, U, CLOCK>;
-    default: *grid = 0; return nullptr;
+    case 128: g = 16; fn = k_hops_big<7, 1, U, CLOCK>; break;
+    case 256:
+      if (spread == 16) {
+        g = 16;
+        fn = k_hops_big<8, 4, U, CLOCK>;
+      } else {
+        g = 64;
+        fn = k_hops_big<8, 1, U, CLOCK>;
+      }
+      break;
+    case 512: g = 64; fn = k_hops_big<9, 4, U, CLOCK>; break;
+    case 1024: g = 128; fn = k_hops_big<10, 8, U, CLOCK>; break;
+    case 2048: g = 256; fn = k_hops_big<11, 16, U, CLOCK>; break;
+    default: return nullptr;
   }
+  if (spread != 0 && spread != g) return nullptr;
+  *grid = g;
+  return fn;
 }
 
-BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t* grid) {
-  if (clock != CG_CLOCK_DET) return U == 1 ? pick_big_uc<1, 1>(L, grid) : pick_big_uc<2, 1>(L, grid);
-  return U == 1 ? pick_big_uc<1, 0>(L, grid) : pick_big_uc<2, 0>(L, grid);
+BigFn pick_big(int32_t L, int32_t U, int32_t clock, int32_t spread, int32_t* grid) {
+  if (clock != CG_CLOCK_DET) return U == 1 ? pick_big_uc<1, 1>(L, spread, grid) : pick_big_uc<2, 1>(L, spread, grid);
+  return U == 1 ? pick_big_uc<1, 0>(L, spread, grid) : pick_big_uc<2, 0>(L, spread, grid);
 }
 
 // Label-parallel kernel for one sample of side L (a replica per workgroup).
@@ -1059,7 +1085,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
         g = p.spread ? p.spread : ncu;
         if (fn) e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, p.lds_hop);
       } else {
-        fn = pick_big(samples[b].L, p.U, p.clock, &g);
+        fn = pick_big(samples[b].L, p.U, p.clock, p.spread, &g);
       }
       int per_cu = 0;
       if (fn) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 1024, p.lds_hop);

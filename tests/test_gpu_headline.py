@@ -9,7 +9,7 @@ logged dx, the clock is s_last / Gamma, and the FP32 drift stays within 1e-5."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import compare_logs, lazy_oracle_of, oracle_of, require_gpu, say
+from tests.gpu_util import compare_logs, compare_logs_fp32, lazy_oracle_of, oracle_of, require_gpu, say
 from workloads import headline
 
 pytestmark = pytest.mark.gpu
@@ -72,8 +72,10 @@ def test_headline_fp32_full_size():
         assert st["refreshes"] >= STEPS and st["max_drift"] <= 1e-5, k
     for k in CHECKED:
         s = samples[k]
-        agree = compare_logs(s, b.hop_log(k), oracle_of(s).run(STEP * STEPS), tol=1e-4)
-        say(f"headline FP32 sample {k}: {agree} hops identical to the oracle")
+        o = oracle_of(s)
+        eps_max = max(float(np.abs(o.eps()).max()), float(np.abs(b.energies(k)).max()))
+        agree = compare_logs_fp32(s, b.hop_log(k), o.run(STEP * STEPS), b.stats(k)["max_drift"], eps_max)
+        say(f"headline FP32 sample {k}: {agree} of {STEP * STEPS} hops identical to the oracle")
         assert agree >= 20
         _check_sampled_energies(b, k, s, 1e-5)
 

@@ -33,6 +33,48 @@ def test_whole_gpu_kernel_hop_for_hop_l128(M):
     assert abs(st["H0"] - sc["H0"]) <= 1e-9 * abs(sc["H0"])
 
 
+def test_whole_gpu_kernel_hop_for_hop_l256_benched_shapes():
+    """L = 256 at T = 0.05 (the large-lattice bench leg's parameters) on the grid the bench times
+    (64 workgroups, one site per thread) and forced onto 16 workgroups (four sites per thread):
+    both execute the full oracle's hops, labels and sites, hop for hop, over launches of several
+    hops, and end with its FP64 energies (1e-12), occupation, dipole, clock and energy."""
+    cg = require_gpu()
+    s = Sample(256, 32768, 1.0, 1.0, 10.0, 0.05, 0.005, 7, 0)
+    pieces = [700, 1, 299, 500]
+    hops = sum(pieces)
+    runs = {}
+    for spread in (0, 16):
+        say(f"whole-GPU kernel L=256 spread={spread}: {hops} hops")
+        b = _batch(cg, [s], precision=cg.CG_FP64, M=1024, spread=spread, log_hops=hops)
+        for n in pieces:
+            b.run_hops(n)
+        runs[spread] = b
+    say("whole-GPU kernel L=256: oracle")
+    o = oracle_of(s)
+    ol = o.run(hops)
+    sc = o.scalars()
+    eps = o.eps()
+    for spread, b in runs.items():
+        say(f"whole-GPU kernel L=256 spread={spread}: compare")
+        assert compare_logs(s, b.hop_log(0), ol) == hops
+        assert np.array_equal(b.occupation(0), o.occ())
+        assert float(np.abs(b.energies(0) - eps).max()) <= 1e-12
+        st = b.stats(0)
+        assert st["P"] == sc["P"] and st["hops"] == hops and st["s_last"] == sc["s_last"]
+        assert abs(st["t"] - sc["t"]) <= 1e-12 * sc["t"]
+        assert abs(st["H0"] - sc["H0"]) <= 1e-9 * abs(sc["H0"])
+
+
+def test_whole_gpu_kernel_refuses_unknown_grids():
+    cg = require_gpu()
+    s = Sample(256, 32768, 1.0, 1.0, 10.0, 0.05, 0.005, 7, 0)
+    for spread in (8, 32, 128):
+        with pytest.raises(cg.CgError):
+            _batch(cg, [s], precision=cg.CG_FP64, spread=spread)
+    with pytest.raises(cg.CgError):  # the per-sample kernels take no workgroup count
+        _batch(cg, [Sample(64, 2048, 1.0, 1.0, 8.0, 0.05, 0.01, 2, 0)], precision=cg.CG_FP64, spread=16)
+
+
 def test_whole_gpu_kernel_odd_and_even_launches():
     """Within a launch the kernel alternates two copies of the occupation and the energy mirror
     (hop k reads copy k % 2) and returns to the first copy at the launch's end.  Launches of
