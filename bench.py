@@ -37,6 +37,9 @@ sys.path.insert(0, ROOT)
 # reads reach 65 B/clk (each LDS read instruction occupies the CU's LDS pipe for ~4-5 cycles
 # whatever its width), and writes at most ~72 B/clk at any width
 LDS_PEAK_GBS = 256 * 224 * 2.4
+# LDS writes: the probe measures at most ~72 B/clk per CU with 8- or 16-byte stores
+LDS_WRITE_BPC = 72.0
+LDS_READ_BPC = 224.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hops_fx_l128_b256_traffic.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1407_5026_amd", "csrc", f) for f in ("hop_fx.hpp", "kernels.hpp", "layout.hpp")]
 
@@ -87,20 +90,35 @@ def _cpu_worker(args):
     return hops, time.perf_counter() - t0
 
 
-def cpu_baseline(warm: int, hops: int, seed: int, cores: int) -> dict:
+def host_cores() -> tuple[int, int]:
+    """(cores the CPU leg uses, cores this process may run on).  The leg uses every core the
+    process may run on, capped at the host share of one GPU (OMP_NUM_THREADS, 16 by default)."""
+    nproc = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS", "16") or 16)
+    return max(1, min(nproc, share)), nproc
+
+
+def cpu_baseline(warm: int, hops: int, seed: int, cores: int, nproc: int) -> dict:
     """The serial FP64 oracle on this host: one headline sample per process, `warm` untimed hops
     from the random start (the GPU's warmup window), then `hops` timed hops; all processes run
-    concurrently and the aggregate is the sum of their rates."""
+    concurrently and the aggregate is the sum of their rates.  Called before this process
+    touches the GPU (the worker processes are forked from it), and the pool is closed and
+    joined, not terminated."""
     import multiprocessing as mp
 
-    with mp.get_context("fork").Pool(cores) as pool:
+    pool = mp.get_context("fork").Pool(cores)
+    try:
         res = pool.map(_cpu_worker, [(b, warm, hops, seed) for b in range(cores)])
+    finally:
+        pool.close()
+        pool.join()
     rate = sum(h / t for h, t in res)
     cpu_s = sum(t for _, t in res)
-    return {"value": rate, "unit": "accepted hops/s", "cores": cores, "kind": "oracle",
+    return {"value": rate, "unit": "accepted hops/s", "cores": cores, "kind": "oracle", "host_nproc": nproc,
             "sample": f"serial FP64 oracle, L=128 T=0.02 E=0.005 rc=10, samples 0..{cores - 1}: "
                       f"hops {warm}..{warm + hops} of each sample timed after {warm} untimed hops from "
-                      f"the random start, {cores} processes, rates summed ({cpu_s:.1f} s of CPU time)"}
+                      f"the random start, {cores} processes on a host where this process may use "
+                      f"{nproc} cores, rates summed ({cpu_s:.1f} s of CPU time)"}
 
 
 def run_form(cg, torch, samples, precision, args, hops_per_step):
@@ -143,6 +161,93 @@ def run_form(cg, torch, samples, precision, args, hops_per_step):
     return dict(seconds=dt, hops=hops, proposals=props, evaluated=evald, theta=theta, hop_ms=hop_ms,
                 hop_launches=hop_n, refresh_ms=ref_ms, refresh_launches=ref_n, max_drift=drift,
                 windows=windows, window_hops=per_win * hops_per_step)
+
+
+def lds_roofline(r: dict, N: int, s_eps: int, kernel: str) -> dict:
+    """LDS roofline of a hop kernel from a timed run.  Algorithmic bytes per accepted hop: the
+    update reads and writes the N energies (N s_eps each way); the proposals read 2 occupancy
+    bytes per serial proposal plus two energies per evaluation that passes the occupancy
+    filter (m_bar and theta_bar are the run's own).  `achieved` = bytes per hop x hops per
+    launch / mean launch time (HIP events on the library's stream); `peak` = the best LDS read
+    rate.  The same bytes against a read/write-split peak: reads at 224 B/clk, the N s_eps
+    written bytes at 72 B/clk, so the split peak is (R + W) / (R / 224 + W / 72) B/clk per CU."""
+    m_bar = r["proposals"] / max(r["hops"], 1)
+    th_bar = r["theta"] / max(r["evaluated"], 1)
+    write_b = N * s_eps
+    read_b = N * s_eps + m_bar * (2 + th_bar * 2 * s_eps)
+    bytes_per_hop = read_b + write_b
+    per_launch_hops = r["hops"] / max(r["hop_launches"], 1)
+    mean_launch_s = r["hop_ms"] / max(r["hop_launches"], 1) * 1e-3
+    achieved = bytes_per_hop * per_launch_hops / mean_launch_s / 1e9
+    split_bpc = bytes_per_hop / (read_b / LDS_READ_BPC + write_b / LDS_WRITE_BPC)
+    split_peak = 256 * split_bpc * 2.4
+    return {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(kernel), "kernel": kernel,
+            "bytes_per_hop": bytes_per_hop, "read_bytes_per_hop": read_b, "write_bytes_per_hop": write_b,
+            "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3,
+            "peak_rw_split": split_peak, "frac_rw_split": achieved / split_peak}
+
+
+def phase_split(cg, torch, samples, args) -> dict:
+    """The paper's split of the time per executed hop into the rejection part W_R (drawing,
+    evaluating and selecting labels) and the update part W_U (step 3b): the headline batch in
+    the FP32 form with the phase-timer instance of the hop kernel (wave 0's shader cycles per
+    phase), one untimed step from the random start, then `args.phase_steps` steps."""
+    opts = cg.make_opts(precision=cg.CG_FP32_REFRESH, M=args.M, block=args.block, K_refresh=args.K,
+                        clock_mode=args.clock, phase_timers=1)
+    b = cg.Batch(samples, opts)
+    n = len(samples)
+    b.run_hops(args.hops_per_step)
+    torch.cuda.synchronize()
+    before = [b.stats(k) for k in range(n)]
+    b.kernel_time()
+    for _ in range(args.phase_steps):
+        b.run_hops(args.hops_per_step)
+    torch.cuda.synchronize()
+    hop_ms, hop_n, _, _ = b.kernel_time()
+    after = [b.stats(k) for k in range(n)]
+    b.close()
+    hops = sum(a["hops"] - c["hops"] for a, c in zip(after, before))
+    cyc = [sum(a["phase_cycles"][i] - c["phase_cycles"][i] for a, c in zip(after, before)) / hops for i in range(4)]
+    total = sum(cyc)
+    # per-sample time per hop: every sample runs on its own CU for the whole launch
+    us_hop = hop_ms * 1e3 / (hops / n)
+    wr = (cyc[0] + cyc[1] + cyc[2]) / total
+    return {"kernel_instance": "phase timers", "hops_per_sample": hops // n,
+            "cycles_per_hop": {"draw": cyc[0], "evaluate": cyc[1], "select_and_execute": cyc[2],
+                               "update": cyc[3]},
+            "us_per_hop_per_sample": us_hop, "W_R_us": wr * us_hop, "W_U_us": (1 - wr) * us_hop,
+            "W_R_frac": wr}
+
+
+def batched_l64(cg, torch, hops: int, step: int) -> dict:
+    """256 samples at L = 64, rc = 8, E = 0.01, T round-robin over {0.02, 0.03, 0.05, 0.08, 0.12},
+    FP32 form, M = 2048, refresh every 2048 hops: `hops` accepted hops per sample from the
+    random start in steps of `step`."""
+    from workloads import batched_l64 as recipe
+
+    samples = recipe(256)
+    b = cg.Batch(samples, cg.make_opts(precision=cg.CG_FP32_REFRESH, M=2048, K_refresh=2048))
+    torch.cuda.synchronize()
+    b.kernel_time()
+    t0 = time.perf_counter()
+    done = 0
+    while done < hops:
+        n = min(step, hops - done)
+        b.run_hops(n)
+        done += n
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hop_ms, hop_n, ref_ms, ref_n = b.kernel_time()
+    st = [b.stats(k) for k in range(len(samples))]
+    b.close()
+    by_T = {}
+    for smp, x in zip(samples, st):
+        by_T.setdefault(smp.T, []).append(x["s_last"] / max(x["hops"], 1))
+    return {"samples": len(samples), "L": 64, "hops_per_sample": hops, "M": 2048, "K_refresh": 2048,
+            "seconds": dt, "hops_per_s": sum(x["hops"] for x in st) / dt, "hop_kernel_ms": hop_ms,
+            "refresh_ms": ref_ms, "max_drift": max(x["max_drift"] for x in st),
+            "m_bar_by_T": {str(T): sum(v) / len(v) for T, v in sorted(by_T.items())}}
 
 
 def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: int = 0, spread: int = 0,
@@ -304,6 +409,10 @@ def main() -> int:
                     help="time a batch of simple cubic samples of this side (FP64 form; 0 = none)")
     ap.add_argument("--cubic-hops", type=int, default=2048)
     ap.add_argument("--cubic-steps", type=int, default=20)
+    ap.add_argument("--l64-hops", type=int, default=200_000,
+                    help="hops per sample of the 256-sample L = 64 temperature-grid batch (0 = none)")
+    ap.add_argument("--phase-steps", type=int, default=4,
+                    help="steps of the phase-timer run that splits a hop into W_R and W_U (0 = none)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before timing, copy this many MiB with a plain device copy (a counter "
                          "calibration point for FETCH_SIZE / WRITE_SIZE runs)")
@@ -313,10 +422,21 @@ def main() -> int:
               f"GPUs without communication); --gpus {args.gpus} is not supported", file=sys.stderr)
         return 2
 
+    from workloads import headline
+
+    cpu = None
+    if not args.skip_cpu:
+        # before this process touches the GPU: the oracle's worker processes are forked from it
+        cores, nproc = host_cores()
+        if args.cpu_cores:
+            cores = args.cpu_cores
+        print(f"[bench] CPU oracle on {cores} cores ({nproc} available)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.warmup * args.hops_per_step, args.cpu_hops, headline(1)[0].seed, cores, nproc)
+        print(f"[bench] CPU oracle done: {cpu['value']:.4g} hops/s", file=sys.stderr, flush=True)
+
     import torch
 
     import paper_1407_5026_amd as cg
-    from workloads import headline
 
     cg.load()
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
@@ -341,16 +461,6 @@ def main() -> int:
         print(f"[bench] FP64 done: {r64['hops'] / r64['seconds']:.4g} hops/s", file=sys.stderr, flush=True)
 
     value = r32["hops"] / r32["seconds"]
-    # LDS roofline of the hop kernel: per accepted hop the update reads and writes N energies
-    # (2 N s_eps bytes) and the proposals read 2 occupancy bytes per serial proposal plus two
-    # energies per proposal that passes the occupancy filter.
-    s_eps = 4
-    m_bar = r32["proposals"] / max(r32["hops"], 1)
-    th_bar = r32["theta"] / max(r32["evaluated"], 1)
-    bytes_per_hop = 2 * N * s_eps + m_bar * (2 + th_bar * 2 * s_eps)
-    per_launch_hops = r32["hops"] / max(r32["hop_launches"], 1)
-    mean_launch_s = r32["hop_ms"] / max(r32["hop_launches"], 1) * 1e-3
-    achieved = bytes_per_hop * per_launch_hops / mean_launch_s / 1e9
     kernel = f"k_hops_fx<128, {1 if args.M <= 1024 else 2}, {0 if args.clock == 0 else 1}, 16, false>"
     out = {
         "metric": "accepted hops/s per GPU (L=128, T=0.02, batched) FP32+refresh vs FP64 PR",
@@ -378,10 +488,7 @@ def main() -> int:
         "refresh_ms_per_step": r32["refresh_ms"] / args.steps,
         "window_hops_per_sample": r32["window_hops"],
         "fp32_window_hops_per_s": [round(v) for v in r32["windows"]],
-        "roofline": {"bound": "lds", "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / LDS_PEAK_GBS, "traffic": measured_traffic(kernel),
-                     "kernel": kernel, "bytes_per_hop": bytes_per_hop,
-                     "hops_per_launch": per_launch_hops, "mean_launch_ms": mean_launch_s * 1e3},
+        "roofline": lds_roofline(r32, N, 4, kernel),
     }
     rec = counter_record(kernel)
     if rec is not None and "valu_insts_per_hop" in rec:
@@ -394,6 +501,7 @@ def main() -> int:
         out["fp64_value"] = r64["hops"] / r64["seconds"]
         out["fp64_window_hops_per_s"] = [round(v) for v in r64["windows"]]
         out["fp64_ms_per_step"] = r64["seconds"] / args.steps * 1e3
+        out["roofline_fp64"] = lds_roofline(r64, N, 8, "k_hops_fx64<128, 1, 0>")
     def leg(name, fn):
         print(f"[bench] {name}", file=sys.stderr, flush=True)
         try:
@@ -402,7 +510,13 @@ def main() -> int:
             print(f"[bench] {name} failed: {e!r}", file=sys.stderr, flush=True)
             return {"error": repr(e)}
 
+    if args.phase_steps:
+        out["phase_split_fp32"] = leg("phase timers (W_R / W_U per hop)",
+                                      lambda: phase_split(cg, torch, samples, args))
     if not args.no_legs:
+        if args.l64_hops:
+            out["batched_l64_fp32"] = leg(f"256 samples L=64 over the T grid, {args.l64_hops} hops each",
+                                          lambda: batched_l64(cg, torch, args.l64_hops, 8192))
         if args.large_L:
             out["large_lattice_fp64"] = [
                 leg(f"whole-GPU sample L={L} T={args.large_T}",
@@ -432,9 +546,8 @@ def main() -> int:
         if args.cubic_L:
             out["cubic_fp64"] = leg(f"cubic batch L={args.cubic_L}",
                                     lambda: cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps))
-    if not args.skip_cpu:
-        cores = args.cpu_cores or min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(args.warmup * args.hops_per_step, args.cpu_hops, samples[0].seed, cores)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
     return 0
 
