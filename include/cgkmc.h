@@ -47,7 +47,10 @@ extern "C" {
 #define CG_ESTALL (-4)   /* label cap reached before the requested hops; state is valid */
 
 #define CG_FP64 0          /* proposals, acceptance and energy update in FP64            */
-#define CG_FP32_REFRESH 1  /* FP32 proposals/update (Kahan-compensated), FP64 refresh every K hops */
+#define CG_FP32_REFRESH 1  /* FP32 proposals and update with each energy kept as an FP32 pair
+                              (exact-geometry kernel: hi + lo renormalised by Fast2Sum every 16
+                              hops; other kernels: Kahan-compensated sums), FP64 refresh every
+                              K hops */
 
 #define CG_CLOCK_DET 0    /* dt = m / Gamma (deterministic increment)                    */
 #define CG_CLOCK_GAUSS 1  /* dt ~ Gaussian(m/Gamma, sqrt(m)/Gamma), clamped at 0 (step 3c) */
@@ -115,7 +118,10 @@ typedef struct cg_run_opts {
                           one sample, a parallel width of the order of 1/A).  The same hops
                           as 1 for any spread                                            */
   int32_t spread;      /* variant 6: workgroups per sample (0 = one per CU; at most the
-                          number that can be co-resident, else CG_ENOSPC); 0 otherwise  */
+                          number that can be co-resident, else CG_ENOSPC).  Whole-GPU
+                          kernel (variant 4 or L > 192): 0 = the size's grid, or that grid's
+                          workgroup count, or 16 at L = 256 (four sites per thread);
+                          CG_EINVAL for other counts.  0 for every other kernel         */
   uint64_t max_labels_per_call; /* stall guard per sample and call; 0 = 2^32            */
 } cg_run_opts;
 
@@ -146,35 +152,74 @@ typedef struct cg_stats {
 
 typedef struct cg_ctx cg_ctx;
 
-/* Device bytes needed for n samples under the given options (alignment 256). */
+/* Device bytes needed for n samples under the given options (alignment 256): per sample the
+ * state of the chain the paper's algorithm carries (occupations and local energies of Eq. 1
+ * and the text after Eq. 2, the dipole, the clock), the proposal tables of the mixed
+ * algorithm's tower sampling (section "Hopping conduction in the Coulomb glass") and the
+ * refresh tables.  Host-only: validates the samples and options like cg_create (CG_EINVAL,
+ * CG_ENOSPC) and writes *bytes. */
 int cg_arena_bytes(const cg_sample_desc* samples, int32_t n, const cg_run_opts* opts,
                    size_t* bytes);
 
-/* Build tables, draw the random initial occupation (a uniform n_electrons-subset) and
- * the disorder phi, and compute the initial local energies
+/* Set up a batch of independent samples of Eq. 1 (section "Hopping conduction in the Coulomb
+ * glass"; the runs of section "Results for the lattice model in two dimensions" start from a
+ * random configuration): build the proposal tables (Gamma^T_ij = exp(-2 r_ij / xi) over the
+ * hop vectors |d| <= rc, tower thresholds, Gamma = N sum_d exp(-2|d|/xi)), draw the random
+ * initial occupation (a uniform n_electrons-subset) and the disorder phi_i uniform in [-W, W],
+ * and compute the initial single-particle energies (definition after Eq. 2)
  *   eps_l = phi_l + sum_{m != l} (n_m - nu) / r_lm
- * in FP64 with m summed in index order, all on the GPU.  `arena` is device memory of
- * at least cg_arena_bytes; `hip_stream` is a hipStream_t (NULL = default stream).
- * Returns CG_OK and *out, or an error (no context is created). */
+ * in FP64 with m summed in index order, all on the GPU.  `samples` (n >= 1 host structs) and
+ * `opts` are read during the call only.  `arena` is caller-owned device memory of at least
+ * cg_arena_bytes (256-byte aligned) that must outlive the context; `hip_stream` is a
+ * hipStream_t (NULL = default stream) on which all later work is enqueued.  Returns CG_OK and
+ * *out; or CG_EINVAL (invalid sample or option), CG_ENOSPC (arena too small, or a sample
+ * does not fit the chosen kernel), CG_EHIP (HIP error); then no context is created. */
 int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_run_opts* opts,
               void* arena, size_t arena_bytes, void* hip_stream);
+/* Release the context's host objects (graphs, events); the arena stays the caller's.
+ * Synchronises the context stream.  NULL is accepted. */
 int cg_destroy(cg_ctx* ctx);
 
-/* Every sample executes exactly n_hops more hops (n_hops >= 1).  Returns CG_ESTALL if a
- * sample reached max_labels_per_call first (its state stays consistent; call again). */
+/* The mixed parallel-rejection algorithm (section "Hopping conduction in the Coulomb glass",
+ * steps 1, 2 and 3a-3c, with the generic scheme of section "Parallel rejection algorithm"):
+ * every sample executes exactly n_hops more hops (n_hops >= 1).  Per parallel iteration the
+ * labels s_last + 1 ... are proposed (step 1), filtered by theta_ij and accepted with
+ * min(1, exp(-dH/T)) (step 2); the lowest accepted label is executed, the dipole and every
+ * local energy updated (steps 3a, 3b) and the clock advanced (step 3c).  In the FP32 form an
+ * FP64 refresh of the energies ends every K_refresh hops.  Enqueued on the context stream
+ * (asynchronous).  Returns CG_OK, CG_EINVAL (n_hops < 1, null context), CG_EHIP, or
+ * CG_ESTALL if a sample reached max_labels_per_call first (its state stays consistent; call
+ * again to continue). */
 int cg_run_hops(cg_ctx* ctx, int64_t n_hops);
-/* Every sample runs until the first hop that brings its clock to t >= t_end (samples
- * already there execute nothing).  Returns CG_ESTALL as above. */
+/* As cg_run_hops, but every sample runs until the first hop that brings its clock (step 3c;
+ * the deterministic, Gaussian or Gamma increment of clock_mode) to t >= t_end; samples
+ * already there execute nothing.  Synchronises the context stream (the stopping test reads
+ * the samples' state).  Returns CG_OK, CG_EINVAL (t_end not finite), CG_EHIP or CG_ESTALL as
+ * above (t_end must be finite and >= 0). */
 int cg_run_time(cg_ctx* ctx, double t_end);
-/* FP32 form: refresh every sample now (FP64 O(N^2) recompute, drift recorded). */
+/* FP32 form: recompute every sample's energies now from their definition after Eq. 2 in FP64
+ * (the refresh that otherwise ends each K_refresh interval) and record the drift
+ * max_l |eps32_l - eps64_l|; in the FP64 form the exact recompute replaces the incrementally
+ * updated energies.  Synchronises the context stream.  CG_OK, CG_EINVAL (null context) or
+ * CG_EHIP. */
 int cg_refresh(cg_ctx* ctx);
 
-/* Set temperature and field of one sample (T > 0). */
+/* Set the temperature T (> 0) and the field E of one sample: the T of Eq. 2's thermal factor
+ * and the E of Eq. 1's field term (-E sum_i n_i x_i, so dH contains -E dx).  Takes effect at
+ * the next run call; the configuration and clock are kept.  Synchronises the context stream.
+ * CG_EINVAL for a bad index, T <= 0 or non-finite values. */
 int cg_set_TE(cg_ctx* ctx, int32_t sample, double T, double E);
 
-/* Host copies: occupation (N bytes), local energies as FP64 (N doubles; the FP32 form
- * returns its value word plus the compensated low part), disorder phi (N doubles),
- * counters. */
+/* Host copies of one sample's state, into caller-owned host memory; each synchronises the
+ * context stream and returns CG_EINVAL for a bad sample index or a null pointer.
+ *   cg_get_occupation: the occupation numbers n_i of Eq. 1 (N bytes, 0 or 1, site
+ *     i = y L + x, or (z L + y) L + x on the cubic lattice);
+ *   cg_get_local_energies: the single-particle energies eps_i (definition after Eq. 2) as N
+ *     doubles; the FP32 form returns its FP32 pair's sum;
+ *   cg_get_phi: the random site energies phi_i of Eq. 1 (N doubles);
+ *   cg_get_stats: the counters of the parallel-rejection run (section "Parallel rejection
+ *     algorithm": iterations p per hop summed, labels evaluated) and the observables (dipole
+ *     change P, clock, Eq. 1 field-free energy, refresh drift). */
 int cg_get_occupation(cg_ctx* ctx, int32_t sample, uint8_t* host_out);
 int cg_get_local_energies(cg_ctx* ctx, int32_t sample, double* host_out);
 int cg_get_phi(cg_ctx* ctx, int32_t sample, double* host_out);
@@ -184,10 +229,15 @@ int cg_get_stats(cg_ctx* ctx, int32_t sample, cg_stats* out);
  * Coulomb glass", step 3c).  Synchronizes the context stream; CG_EINVAL for a bad sample
  * index or a null pointer. */
 int cg_get_clock(cg_ctx* ctx, int32_t sample, double* t);
-/* Clock and current: t, dipole change P and sigma = P / (N E t) (0 if E t == 0). */
+/* Clock and current of one sample: t, the dipole change P = sum of executed dx (step 3b) and
+ * the conductivity sigma = P / (N E t), the average of Eq. 3's sigma(t) = (1/(N E)) dP/dt
+ * over [0, t] (0 if E t == 0).  Synchronises the context stream; CG_EINVAL for a bad index
+ * or a null pointer. */
 int cg_get_current(cg_ctx* ctx, int32_t sample, double* t, int64_t* P, double* sigma);
-/* Executed-hop log of one sample: labels, origin and destination sites, up to `cap`
- * entries; *count receives the number copied. */
+/* Executed-hop log of one sample (step 3a's executed hops i_q -> j_q with their labels q):
+ * labels, origin and destination sites into caller-owned host arrays of `cap` entries each;
+ * *count receives the number copied (at most the log_hops capacity, first hops first).
+ * Synchronises the context stream; CG_EINVAL for a bad index, cap < 0 or null pointers. */
 int cg_get_hop_log(cg_ctx* ctx, int32_t sample, uint64_t* labels, int32_t* from, int32_t* to,
                    int64_t cap, int64_t* count);
 
@@ -220,12 +270,16 @@ int cg_save(cg_ctx* ctx, int32_t sample, void* host_blob, size_t* bytes);
 int cg_load(cg_ctx* ctx, int32_t sample, const void* host_blob, size_t bytes);
 
 /* Device time of the hop kernel launches since the last call (ms) and launch count, and
- * the same for refreshes; resets them.  Timing uses HIP events on the context stream; with
- * use_graph, each replay is timed as a whole and added to the hop time. */
+ * the same for refreshes; resets them (the per-hop wall-clock cost the paper splits into
+ * W_R and W_U in section "Code performance").  Timing uses HIP events on the context
+ * stream; with use_graph, each replay is timed as a whole and added to the hop time.
+ * Waits for the recorded events; null outputs are skipped. */
 int cg_take_kernel_time(cg_ctx* ctx, double* hop_ms, int64_t* hop_launches, double* refresh_ms,
                         int64_t* refresh_launches);
 
-/* Autotuner: chooses opts->M (the kernel's label chunk, 1024 or 2048) by the hop-kernel
+/* Autotuner of the parallel width (section "Parallel rejection algorithm": the best M is of
+ * the order of min(1/A, C), the inverse acceptance or the parallel capacity): chooses opts->M
+ * (the kernel's label chunk, 1024 or 2048) by the hop-kernel
  * time of trial runs of trial_hops hops, and, in the FP32 form, opts->K_refresh as the
  * largest of 8192, 4096, 2048, 1024 whose drift over 2K hops from the initial state stays
  * below drift_target / 2 (else 1024).  Each trial creates and destroys a context on
