@@ -37,7 +37,8 @@ def build(verbose: bool = False) -> str:
 
 
 def build_probe(verbose: bool = False) -> str:
-    """The unit-throughput probe behind the roofline denominators (a standalone program)."""
+    """The unit-throughput probe behind the roofline denominators (a standalone program, run
+    as ./paper_1407_5026_amd/lds_probe; not part of the library build)."""
     tmp = PROBE + ".tmp"
     flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
     cmd = [HIPCC, *flags, "-o", tmp, PROBE_SRC]
@@ -51,5 +52,9 @@ def build_probe(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
-    print(build_probe(verbose=True))
+    import sys
+
+    if sys.argv[1:] == ["probe"]:
+        print(build_probe(verbose=True))
+    else:
+        print(build(verbose=True))

@@ -1,10 +1,10 @@
 // lds_probe.hip -- throughput of the gfx950 units the hop kernels use, for the roofline
-// denominators: LDS reads and writes of 4/8/16 bytes per lane, the hop
-// kernel's update pattern (per lane 32 table reads in pairs and 16 value stores, and two
-// table layouts with 16-byte value stores), FP32
-// multiplies, 32x32->64-bit integer multiplies and log2.  One workgroup of 1024 threads per
-// CU; every address stays inside the workgroup's LDS array; loop-carried offsets are opaque
-// to the compiler so that no load is hoisted out of the timed loop.
+// denominators: LDS reads and writes of 4/8/16 bytes per lane, random 4-byte reads, the
+// 16-wave workgroup barrier, FP32 multiplies, 32x32->64-bit integer multiplies and log2
+// (one workgroup of 1024 threads per CU; every address stays inside the workgroup's LDS
+// array; loop-carried offsets are opaque to the compiler so that no load is hoisted out of
+// the timed loop), and with the argument `barrier` the whole-GPU hop kernel's grid barrier
+// on 64, 128 and 256 workgroups.  Build: python paper_1407_5026_amd/build.py probe.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -104,139 +104,6 @@ __global__ void __launch_bounds__(1024) k_write(uint32_t* out, int iters) {
   if (buf[threadIdx.x] == 0x12345678u) out[blockIdx.x * 1024 + threadIdx.x] = 1;
 }
 
-// The hop kernel's update at L = 128: per lane two table bases (rows 1088 floats apart, two
-// columns 17 floats apart) and 16 stores (rows 2048 floats apart, columns 64 apart).
-constexpr int kUpdWords = 34816;  // 136 KB: 16384 value words + table rows
-__global__ void __launch_bounds__(1024) k_update(uint32_t* out, int iters) {
-  extern __shared__ __align__(16) float sm[];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = threadIdx.x; k < kUpdWords; k += 1024) sm[k] = k * 1e-3f;
-  __syncthreads();
-  float acc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-  for (int it = 0; it < iters; ++it) {
-    // largest index: 16384 + 52 * 68 + 63 + 7 * 1088 + 17 = 27616 < kUpdWords
-    const int bj = opaque_int(16384 + wid * 68 + ((lane * 3 + it) & 63));
-    const int bi = opaque_int(16384 + (wid + 37) * 68 + ((lane * 5 + it) & 63));
-    float d[16];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) d[2 * r + c] = sm[bj + r * 1088 + c * 17] - sm[bi + r * 1088 + c * 17];
-    }
-    const int ev = opaque_int(wid * 128 + lane);  // largest store index 1983 + 14336 + 64 < 16384
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        acc[2 * r + c] += d[2 * r + c];
-        sm[ev + r * 2048 + c * 64] = acc[2 * r + c];
-      }
-    }
-  }
-  float s = 0.f;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) s += acc[k];
-  if (s == 1.2345f) out[blockIdx.x * 1024 + threadIdx.x] = 1;
-}
-
-typedef float probe_f4 __attribute__((ext_vector_type(4)));
-
-// The update with 16-byte value stores (four per lane, chunk-major) and two table layouts at
-// L = 128.  rows: table rows 68 floats wide by raw row difference, two folded columns per
-// lane, rows 16 apart read in pairs (16 two-address reads per lane).  pairs: per column pair
-// (c, 64 - c) and row, two floats side by side; a lane's 8 rows (one residue class mod 16)
-// are 8 consecutive pairs, read as 4 double-pair reads per base (8 per lane).
-// cols: the table column-major (260 floats per folded column, raw row difference inside), a
-// wave owning 8 consecutive rows: a lane's 8 rows per column are 8 consecutive floats, read
-// as three aligned 16-byte loads (12 per lane).
-template <int LAYOUT, bool STORES = true>  // 0 rows, 1 pairs, 2 cols; STORES off: reads only
-__global__ void __launch_bounds__(1024) k_update_layout(uint32_t* out, int iters) {
-  extern __shared__ __align__(16) float sm[];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int k = threadIdx.x; k < kUpdWords; k += 1024) sm[k] = k * 1e-3f;
-  __syncthreads();
-  float acc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.f;
-  for (int it = 0; it < iters; ++it) {
-    const int yj = it & 127, yi = (it * 5 + 3) & 127, xj = (it * 7) & 127, xi = (it * 11 + 1) & 127;
-    const int dj = (lane - xj) & 127, di = (lane - xi) & 127;
-    const int cj = dj < 128 - dj ? dj : 128 - dj, ci = di < 128 - di ? di : 128 - di;  // 0..64
-    float d[16];
-    if constexpr (LAYOUT == 2) {
-      const int dj1 = (lane + 64 - xj) & 127, di1 = (lane + 64 - xi) & 127;
-      const int cj1 = dj1 < 128 - dj1 ? dj1 : 128 - dj1, ci1 = di1 < 128 - di1 ? di1 : 128 - di1;
-      const int sj = 8 * wid - yj + 128, si = 8 * wid - yi + 128;  // 1..248
-      // largest index 16384 + 64 * 260 + 248 + 11 = 33283 < kUpdWords
-      const int aj0 = opaque_int((16384 + cj * 260 + sj) >> 2) * 4, aj1 = opaque_int((16384 + cj1 * 260 + sj) >> 2) * 4;
-      const int ai0 = opaque_int((16384 + ci * 260 + si) >> 2) * 4, ai1 = opaque_int((16384 + ci1 * 260 + si) >> 2) * 4;
-      float fj0[12], fj1[12], fi0[12], fi1[12];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const probe_f4 a = *(const probe_f4*)&sm[aj0 + 4 * k], b = *(const probe_f4*)&sm[aj1 + 4 * k];
-        const probe_f4 c = *(const probe_f4*)&sm[ai0 + 4 * k], e = *(const probe_f4*)&sm[ai1 + 4 * k];
-        fj0[4 * k] = a.x; fj0[4 * k + 1] = a.y; fj0[4 * k + 2] = a.z; fj0[4 * k + 3] = a.w;
-        fj1[4 * k] = b.x; fj1[4 * k + 1] = b.y; fj1[4 * k + 2] = b.z; fj1[4 * k + 3] = b.w;
-        fi0[4 * k] = c.x; fi0[4 * k + 1] = c.y; fi0[4 * k + 2] = c.z; fi0[4 * k + 3] = c.w;
-        fi1[4 * k] = e.x; fi1[4 * k + 1] = e.y; fi1[4 * k + 2] = e.z; fi1[4 * k + 3] = e.w;
-      }
-      // the kernel picks 8 of the 12 floats by a uniform shift; here every float is used
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        d[k] = (fj0[k] - fi0[k]) + (fj0[k + 4] - fi0[k + 4]);
-        d[8 + k] = (fj1[k] - fi1[k]) + (fj1[k + 4] - fi1[k + 4]);
-      }
-    } else if constexpr (LAYOUT == 1) {
-      // pair column min(c, 64 - c) in 0..32, 516 floats each; start pair in 0..248
-      const int pj = cj < 64 - cj ? cj : 64 - cj, pi = ci < 64 - ci ? ci : 64 - ci;
-      const int bj = wid - yj + 128, bi = wid - yi + 128;  // 1..143
-      const int aj = opaque_int(16384 + pj * 516 + 2 * ((bj & 15) * 16 + (bj >> 4)));
-      const int ai = opaque_int(16384 + pi * 516 + 2 * ((bi & 15) * 16 + (bi >> 4)));
-      // largest index 16384 + 32 * 516 + 2 * 248 + 15 = 33407 < kUpdWords
-      const float2* qj = (const float2*)&sm[aj];
-      const float2* qi = (const float2*)&sm[ai];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const float2 vj = qj[k], vi = qi[k];
-        d[2 * k] = vj.x - vi.x;
-        d[2 * k + 1] = vj.y - vi.y;
-      }
-    } else {
-      const int dj1 = (lane + 64 - xj) & 127, di1 = (lane + 64 - xi) & 127;
-      const int cj1 = dj1 < 128 - dj1 ? dj1 : 128 - dj1, ci1 = di1 < 128 - di1 ? di1 : 128 - di1;
-      const int rj = 16384 + (wid - yj + 128) * 68, ri = 16384 + (wid - yi + 128) * 68;
-      const int aj0 = opaque_int(rj + cj), aj1 = opaque_int(rj + cj1);
-      const int ai0 = opaque_int(ri + ci), ai1 = opaque_int(ri + ci1);
-      // largest index 16384 + 143 * 68 + 64 + 7 * 1088 = 33788 < kUpdWords
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        d[2 * r] = sm[aj0 + r * 1088] - sm[ai0 + r * 1088];
-        d[2 * r + 1] = sm[aj1 + r * 1088] - sm[ai1 + r * 1088];
-      }
-    }
-    const int ev = opaque_int(wid * 256 + lane) * 4;  // largest 15360 + 252 + 768 + 3 < 16384
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      probe_f4 w;
-      acc[4 * q] += d[4 * q];
-      acc[4 * q + 1] += d[4 * q + 1];
-      acc[4 * q + 2] += d[4 * q + 2];
-      acc[4 * q + 3] += d[4 * q + 3];
-      w.x = acc[4 * q];
-      w.y = acc[4 * q + 1];
-      w.z = acc[4 * q + 2];
-      w.w = acc[4 * q + 3];
-      if constexpr (STORES) *(probe_f4*)&sm[ev + 256 * q] = w;
-    }
-  }
-  float s = 0.f;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) s += acc[k];
-  if (s == 1.2345f) out[blockIdx.x * 1024 + threadIdx.x] = 1;
-}
-
 __global__ void __launch_bounds__(1024) k_fmul(float* out, int iters) {
   float a[8];
 #pragma unroll
@@ -298,19 +165,8 @@ __global__ void __launch_bounds__(1024) k_log2(float* out, int iters) {
 constexpr uint32_t kGbarSpins = 1u << 20;
 constexpr int kLine = 32;  // words per 128-byte line: one flag or counter per line
 
-__device__ __forceinline__ uint32_t ld_acq(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ bool spin_until(const uint32_t* p, uint32_t target) {
-  uint32_t spins = 0;
-  while (ld_acq(p) < target) {
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins >= kGbarSpins) return false;
-  }
-  return true;
 }
 // relaxed polls (no cache maintenance per poll)
 __device__ __forceinline__ bool spin_rlx(const uint32_t* p, uint32_t target) {
@@ -322,87 +178,28 @@ __device__ __forceinline__ bool spin_rlx(const uint32_t* p, uint32_t target) {
   return true;
 }
 
-// MODE 0: one counter, every workgroup adds 1 and polls it.
-// MODE 1: per-workgroup arrival flags (own line each) polled by workgroup 0's threads, which
-//         then store the release generation that everyone polls.
-// MODE 2: 8 group counters (workgroup g in group g % 8) whose last arriver adds 1 to a top
-//         counter; the top's last arriver stores the release generation.
-// MODE 3: one counter, release add, relaxed polls, one acquire fence after the wait.
-// MODE 4: one counter, relaxed add and polls, no fence (the cost of the atomics alone).
-// MODE 5: MODE 2's tree with a release add, relaxed polls and one acquire fence.
-template <int MODE>
+// The whole-GPU hop kernel's grid barrier: 8 group counters (workgroup g in group g % 8)
+// whose last arriver adds 1 to a top counter, the top's last arriver storing the release
+// generation; release adds, relaxed polls and one acquire fence after the wait.
 __global__ void __launch_bounds__(1024) k_gbar(uint32_t* sync, uint32_t* fail, int iters) {
   __shared__ uint32_t ok;
   const uint32_t G = gridDim.x, g = blockIdx.x;
   uint32_t* rel = sync;                       // release generation
-  uint32_t* top = sync + kLine;               // MODE 0 counter / MODE 2 top counter
-  uint32_t* grp = sync + 2 * kLine;           // MODE 2: 8 group counters
-  uint32_t* flag = sync + 10 * kLine;         // MODE 1: G arrival flags
+  uint32_t* top = sync + kLine;               // top counter
+  uint32_t* grp = sync + 2 * kLine;           // 8 group counters
   const uint32_t gsize = (G + 7 - (g & 7)) / 8;  // workgroups in this one's group
   for (uint32_t it = 1; it <= (uint32_t)iters; ++it) {
     __syncthreads();
     bool good = true;
-    if (MODE == 0) {
-      if (threadIdx.x == 0) {
-        __threadfence();
-        atomicAdd(top, 1u);
-        good = spin_until(top, it * G);
-        __threadfence();
+    if (threadIdx.x == 0) {
+      const uint32_t old = __hip_atomic_fetch_add(grp + (g & 7) * kLine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == it * gsize - 1) {
+        const uint32_t ngroups = G < 8 ? G : 8;
+        const uint32_t o2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (o2 == it * ngroups - 1) __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-    } else if (MODE == 1) {
-      if (threadIdx.x == 0) {
-        __threadfence();
-        __hip_atomic_store(flag + g * kLine, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (g == 0) {
-        if (threadIdx.x < G) good = spin_until(flag + threadIdx.x * kLine, it);
-        good = __syncthreads_and(good);
-        if (threadIdx.x == 0 && good) {
-          __threadfence();
-          __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      if (threadIdx.x == 0 && good) {
-        good = spin_until(rel, it);
-        __threadfence();
-      }
-    } else if (MODE == 3) {
-      if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        good = spin_rlx(top, it * G);
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-      }
-    } else if (MODE == 4) {
-      if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        good = spin_rlx(top, it * G);
-      }
-    } else if (MODE == 5) {
-      if (threadIdx.x == 0) {
-        const uint32_t old = __hip_atomic_fetch_add(grp + (g & 7) * kLine, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == it * gsize - 1) {
-          const uint32_t ngroups = G < 8 ? G : 8;
-          const uint32_t o2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (o2 == it * ngroups - 1) __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        good = spin_rlx(rel, it);
-        __atomic_thread_fence(__ATOMIC_ACQUIRE);
-      }
-    } else {
-      if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t old = atomicAdd(grp + (g & 7) * kLine, 1u);
-        if (old == it * gsize - 1) {
-          const uint32_t ngroups = G < 8 ? G : 8;
-          const uint32_t o2 = atomicAdd(top, 1u);
-          if (o2 == it * ngroups - 1) {
-            __threadfence();
-            __hip_atomic_store(rel, it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-        }
-        good = spin_until(rel, it);
-        __threadfence();
-      }
+      good = spin_rlx(rel, it);
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
     }
     if (threadIdx.x == 0) ok = good ? 1u : 0u;
     __syncthreads();
@@ -425,10 +222,8 @@ static int run_grid_barriers(int ncu) {
   const int iters = 2000;
   for (int G : {64, 128, 256}) {
     if (G > ncu) break;
-    for (int mode = 0; mode < 6; ++mode) {
-      void* const fns[6] = {(void*)k_gbar<0>, (void*)k_gbar<1>, (void*)k_gbar<2>,
-                            (void*)k_gbar<3>, (void*)k_gbar<4>, (void*)k_gbar<5>};
-      void* fn = fns[mode];
+    {
+      void* fn = (void*)k_gbar;
       int it = iters;
       void* args[] = {&sync, &fail, &it};
       float ms = 0.f;
@@ -444,10 +239,7 @@ static int run_grid_barriers(int ncu) {
       }
       uint32_t nf = 0;
       CHK(hipMemcpy(&nf, fail, 4, hipMemcpyDeviceToHost));
-      const char* const names[6] = {"one counter", "flags + master", "8 group counters",
-                                    "counter, release add, relaxed polls, one acquire",
-                                    "counter, relaxed, no fence", "8 groups, release add, relaxed polls, one acquire"};
-      std::printf("grid barrier mode %d (%s), %3d workgroups  %7.2f us per barrier%s\n", mode, names[mode], G,
+      std::printf("grid barrier (8 group counters + top), %3d workgroups  %7.2f us per barrier%s\n", G,
                   ms * 1e3 / iters, nf ? "  (a wait gave up)" : "");
     }
   }
@@ -467,12 +259,6 @@ int main(int argc, char** argv) {
   hipEvent_t e0, e1;
   CHK(hipEventCreate(&e0));
   CHK(hipEventCreate(&e1));
-  CHK(hipFuncSetAttribute((const void*)k_update, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
-  CHK(hipFuncSetAttribute((const void*)k_update_layout<0>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
-  CHK(hipFuncSetAttribute((const void*)k_update_layout<1>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
-  CHK(hipFuncSetAttribute((const void*)k_update_layout<2>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
-  CHK(hipFuncSetAttribute((const void*)k_update_layout<0, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
-  CHK(hipFuncSetAttribute((const void*)k_update_layout<2, false>, hipFuncAttributeMaxDynamicSharedMemorySize, kUpdWords * 4));
   const int iters = 20000;
   float ms = 0.f;
   auto timed = [&](auto launch) -> int {
@@ -506,23 +292,6 @@ int main(int argc, char** argv) {
   std::printf("ds_write_b64  %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 8));
   if (timed([&] { hipLaunchKernelGGL(k_write<4>, g, b, 0, 0, out, iters); })) return 1;
   std::printf("ds_write_b128 %8.3f ms  %7.1f B/clk\n", ms, per_cu(lane_ops * 16));
-  const int upd_iters = iters / 8;
-  if (timed([&] { hipLaunchKernelGGL(k_update, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
-  std::printf("update        %8.3f ms  %7.1f B/clk  %6.0f clk per pass (32 reads + 16 stores per lane)\n", ms,
-              per_cu((double)ncu * 1024 * upd_iters * 48 * 4), ms * 1e-3 * clk / upd_iters);
-  if (timed([&] { hipLaunchKernelGGL(k_update_layout<0>, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
-  std::printf("update, row table    %8.3f ms  %6.0f clk per pass (16 paired 4-byte reads, 4 16-byte stores per lane)\n",
-              ms, ms * 1e-3 * clk / upd_iters);
-  if (timed([&] { hipLaunchKernelGGL(k_update_layout<1>, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
-  std::printf("update, pair table   %8.3f ms  %6.0f clk per pass (8 paired 8-byte reads, 4 16-byte stores per lane)\n",
-              ms, ms * 1e-3 * clk / upd_iters);
-  if (timed([&] { hipLaunchKernelGGL(k_update_layout<2>, g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
-  std::printf("update, column table %8.3f ms  %6.0f clk per pass (12 16-byte reads, 4 16-byte stores per lane)\n",
-              ms, ms * 1e-3 * clk / upd_iters);
-  if (timed([&] { hipLaunchKernelGGL((k_update_layout<0, false>), g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
-  std::printf("update reads only, row table    %8.3f ms  %6.0f clk per pass\n", ms, ms * 1e-3 * clk / upd_iters);
-  if (timed([&] { hipLaunchKernelGGL((k_update_layout<2, false>), g, b, kUpdWords * 4, 0, out, upd_iters); })) return 1;
-  std::printf("update reads only, column table %8.3f ms  %6.0f clk per pass\n", ms, ms * 1e-3 * clk / upd_iters);
   const double wave_ops = (double)ncu * 16 * iters * 64;  // wave instructions per kernel
   if (timed([&] { hipLaunchKernelGGL(k_fmul, g, b, 0, 0, (float*)out, iters); })) return 1;
   std::printf("v_mul_f32     %8.3f ms  %7.2f wave instr/clk\n", ms, wave_ops / (ms * 1e-3) / ncu / clk);
