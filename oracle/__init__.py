@@ -40,13 +40,14 @@ def build(force: bool = True) -> str:
 class _Params(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_e", C.c_int32), ("W", C.c_double), ("xi", C.c_double),
                 ("rc", C.c_double), ("T", C.c_double), ("E", C.c_double),
-                ("seed", C.c_uint64), ("sample_id", C.c_uint32), ("clock_mode", C.c_int32)]
+                ("seed", C.c_uint64), ("sample_id", C.c_uint32), ("clock_mode", C.c_int32),
+                ("pair", C.c_double)]
 
 
 class _Scalars(C.Structure):
     _fields_ = [("s_last", C.c_uint64), ("s_scan", C.c_uint64), ("hops", C.c_uint64),
                 ("P", C.c_int64), ("t", C.c_double), ("H0", C.c_double),
-                ("theta_pass", C.c_uint64), ("Gamma", C.c_double)]
+                ("theta_pass", C.c_uint64), ("Gamma", C.c_double), ("Gamma_lab", C.c_double)]
 
 
 _lib = None
@@ -79,13 +80,17 @@ def _bind(path: str):
     L.or_set_occ.argtypes = [C.c_void_p, P(C.c_uint8)]
     L.or_set_occ.restype = C.c_int
     L.or_run.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_int64, P(C.c_uint64),
-                         P(C.c_int32), P(C.c_int32), C.c_int64]
+                         P(C.c_int32), P(C.c_int32), C.c_int64, P(C.c_int64)]
     L.or_run.restype = C.c_int64
     L.or_recompute_eps.argtypes = [C.c_void_p, P(C.c_double)]
     L.or_energy.argtypes = [C.c_void_p]
     L.or_energy.restype = C.c_double
     L.or_move.argtypes = [C.c_void_p, C.c_int32, C.c_int32, P(C.c_double)]
     L.or_move.restype = C.c_double
+    L.or_draw_label.argtypes = [C.c_void_p, C.c_uint64, P(C.c_int32), P(C.c_int32), P(C.c_int32),
+                                P(C.c_int32), P(C.c_int32), P(C.c_double)]
+    L.or_move_pair.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, P(C.c_double)]
+    L.or_move_pair.restype = C.c_double
     L.or_acceptance.argtypes = [C.c_void_p]
     L.or_acceptance.restype = C.c_double
     L.or_naive_run.argtypes = [C.c_void_p, C.c_double]
@@ -172,12 +177,12 @@ class Oracle:
     """One sample of the serial chain (FP64)."""
 
     def __init__(self, L, n_e, W=1.0, xi=1.0, rc=6.0, T=0.1, E=0.0, seed=1, sample_id=0,
-                 clock_mode=0, lazy=False):
+                 clock_mode=0, lazy=False, pair=0.0):
         """lazy=True: occupation, disorder and proposal law only (no O(N^2) energies; run()
         is unavailable, site_eps() works) -- for lattices too large for the full recompute."""
         self.params = dict(L=L, n_e=n_e, W=W, xi=xi, rc=rc, T=T, E=E, seed=seed,
-                           sample_id=sample_id, clock_mode=clock_mode)
-        p = _Params(L, n_e, W, xi, rc, T, E, seed, sample_id, clock_mode)
+                           sample_id=sample_id, clock_mode=clock_mode, pair=pair)
+        p = _Params(L, n_e, W, xi, rc, T, E, seed, sample_id, clock_mode, pair)
         h = C.c_void_p()
         rc_ = (lib().or_create_lazy if lazy else lib().or_create)(C.byref(p), C.byref(h))
         if rc_ != 0:
@@ -243,18 +248,35 @@ class Oracle:
             raise ValueError("occupation must hold exactly n_e ones")
 
     def run(self, n_hops: int = 0, t_end: float = -1.0, max_labels: int = 0, log_cap: int | None = None):
-        """Advance the chain; returns the hop log (labels, i, j) of this call."""
-        cap = n_hops if log_cap is None else log_cap
+        """Advance the chain; returns the log (labels, i, j) of this call's executed hops (a pair
+        hop logs two entries with its label).  The default capacity holds every entry."""
+        cap = 2 * n_hops if log_cap is None else log_cap
         cap = max(int(cap), 0)
         lab = np.zeros(max(cap, 1), np.uint64)
         li = np.zeros(max(cap, 1), np.int32)
         lj = np.zeros(max(cap, 1), np.int32)
+        nlog = C.c_int64()
         done = lib().or_run(self._h, n_hops, t_end, max_labels, _ptr(lab, C.c_uint64),
-                            _ptr(li, C.c_int32), _ptr(lj, C.c_int32), cap)
+                            _ptr(li, C.c_int32), _ptr(lj, C.c_int32), cap, C.byref(nlog))
         if done < 0:
             raise ValueError("run() needs the energies: this oracle was created lazy")
-        k = min(done, cap)
+        self.last_run_hops = int(done)
+        k = min(nlog.value, cap)
         return lab[:k].copy(), li[:k].copy(), lj[:k].copy()
+
+    def draw_label(self, s: int):
+        """(is_pair, i, v1, ve, v2, u) of label s (ve = v2 = -1 for a single-hop label)."""
+        ip, i, v1, ve, v2, u = (C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(),
+                                C.c_double())
+        lib().or_draw_label(self._h, s, C.byref(ip), C.byref(i), C.byref(v1), C.byref(ve), C.byref(v2),
+                            C.byref(u))
+        return ip.value, i.value, v1.value, ve.value, v2.value, u.value
+
+    def move_pair(self, i: int, v1: int, ve: int, v2: int):
+        """(acceptance probability, dH) of a pair proposal in the current configuration."""
+        dH = C.c_double()
+        p = lib().or_move_pair(self._h, i, v1, ve, v2, C.byref(dH))
+        return p, dH.value
 
     def naive_run(self, t_end: float) -> int:
         """Naive serial KMC until the clock reaches t_end; returns the hops executed."""
@@ -289,7 +311,7 @@ class Oracle3D:
 
     def __init__(self, L, n_e, W=1.0, xi=1.0, rc=2.0, T=0.1, E=0.0, seed=1, sample_id=0):
         self.params = dict(L=L, n_e=n_e, W=W, xi=xi, rc=rc, T=T, E=E, seed=seed, sample_id=sample_id)
-        p = _Params(L, n_e, W, xi, rc, T, E, seed, sample_id, 0)
+        p = _Params(L, n_e, W, xi, rc, T, E, seed, sample_id, 0, 0.0)
         h = C.c_void_p()
         rc_ = lib().or3_create(C.byref(p), C.byref(h))
         if rc_ != 0:

@@ -38,7 +38,7 @@ void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3, TAG_GAMMA = 4, TAG_NAIVE = 5 };
+enum { TAG_PROPOSE = 0, TAG_OCC = 1, TAG_PHI = 2, TAG_CLOCK = 3, TAG_GAMMA = 4, TAG_NAIVE = 5, TAG_PAIR = 6 };
 
 static void stream(const or_state* st, uint64_t idx, uint32_t tag, uint32_t w[4]);
 
@@ -63,6 +63,11 @@ struct or_state {
   int32_t* vec_dx;
   int32_t* vec_dy;
   double wsum, Gamma;
+  /* pair hops: orbit thresholds of the uniform law over the hop vectors (partner offset),
+   * the threshold of the pair choice, and the label rate Gamma / (1 - pair) */
+  uint64_t* thr_u;
+  uint64_t thr_pair;
+  double Gamma_lab;
   /* 1/r by separation: invr[(ddy mod L) * L + (ddx mod L)] */
   double* invr;
   /* configuration */
@@ -149,10 +154,11 @@ static int build_tower(or_state* st) {
   st->orb_size = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   st->orb_first = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
   st->thr = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+  st->thr_u = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
   st->vec_dx = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * 8);
   st->vec_dy = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * 8);
   double* cum = (double*)malloc(sizeof(double) * (size_t)n);
-  if (!st->orb_r2 || !st->orb_size || !st->orb_first || !st->thr || !st->vec_dx ||
+  if (!st->orb_r2 || !st->orb_size || !st->orb_first || !st->thr || !st->thr_u || !st->vec_dx ||
       !st->vec_dy || !cum) { free(reps); free(cum); return -2; }
 
   int32_t nv = 0;
@@ -187,6 +193,10 @@ static int build_tower(or_state* st) {
   for (int32_t o = 0; o + 1 < n; ++o)
     st->thr[o] = (uint64_t)floor(ldexp(cum[o] / acc, 32));
   st->thr[n - 1] = (uint64_t)1 << 32;
+  /* uniform law over the nv hop vectors by orbit: cumulative orbit sizes */
+  for (int32_t o = 0; o + 1 < n; ++o)
+    st->thr_u[o] = ((uint64_t)(st->orb_first[o] + st->orb_size[o]) << 32) / (uint64_t)nv;
+  st->thr_u[n - 1] = (uint64_t)1 << 32;
   /* Gamma = sum_i sum_{j != i} Gamma^T_ij = N * sum_d exp(-2|d|/xi) */
   st->Gamma = (double)st->N * acc;
   free(reps);
@@ -291,6 +301,7 @@ static int create(const or_params* p, or_state** out, int32_t lazy) {
   if (!(p->T > 0.0) || !(p->xi > 0.0) || !(p->W >= 0.0)) return -1;
   if (!(p->rc >= 1.0) || !(2.0 * p->rc < (double)p->L)) return -1;
   if (p->clock_mode < 0 || p->clock_mode > 2) return -1;
+  if (!(p->pair >= 0.0) || !(p->pair < 1.0)) return -1;
 
   or_state* st = (or_state*)calloc(1, sizeof(or_state));
   if (!st) return -2;
@@ -299,6 +310,10 @@ static int create(const or_params* p, or_state** out, int32_t lazy) {
   st->lazy = lazy;
   st->nu = (double)p->n_e / (double)N;
   int rc = build_tower(st);
+  if (rc == 0) {
+    st->thr_pair = (uint64_t)floor(ldexp(p->pair, 32));
+    st->Gamma_lab = st->Gamma / (1.0 - p->pair);
+  }
   st->invr = (double*)malloc(sizeof(double) * (size_t)N);
   st->n = (uint8_t*)calloc((size_t)N, 1);
   st->phi = (double*)malloc(sizeof(double) * (size_t)N);
@@ -343,7 +358,7 @@ int or_create_lazy(const or_params* p, or_state** out) { return create(p, out, 1
 
 void or_destroy(or_state* st) {
   if (!st) return;
-  free(st->orb_r2); free(st->orb_size); free(st->orb_first); free(st->thr);
+  free(st->orb_r2); free(st->orb_size); free(st->orb_first); free(st->thr); free(st->thr_u);
   free(st->vec_dx); free(st->vec_dy); free(st->invr);
   free(st->n); free(st->phi); free(st->eps);
   free(st);
@@ -379,6 +394,7 @@ void or_get_scalars(const or_state* st, or_scalars* out) {
   out->H0 = st->H0;
   out->theta_pass = st->theta_pass;
   out->Gamma = st->Gamma;
+  out->Gamma_lab = st->Gamma_lab;
 }
 
 int or_set_occ(or_state* st, const uint8_t* n) {
@@ -445,6 +461,106 @@ double or_acceptance(const or_state* st) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Pair hops.  The paper considers single-electron hops only (Eq. 2) and names
+ * multi-electron hops as an extension its code can take (sections "Code
+ * performance" and "Conclusions") without giving their rates.  The reading
+ * implemented here: a pair hop moves two electrons at once, i -> j and k -> l (four
+ * distinct sites), with a rate of Eq. 2's form,
+ *   Gamma_{ij,kl} = lambda theta_ij theta_kl exp(-2 (r_ij + r_kl) / xi) min(1, exp(-dH/T)),
+ * restricted to compact pairs: the two starting sites and the two final sites are each
+ * within the hop cutoff of one another (|k - i| <= rc and |l - j| <= rc, minimum image).
+ * dH is the change of Eq. 1's H; moving i -> j and then k -> l with the energies updated
+ * in between (step 3b) gives
+ *   dH = dH_ij + dH_kl + 1/r_ik + 1/r_jl - 1/r_il - 1/r_jk.
+ * The mixed algorithm's factorisation carries over: the tunnelling part is configuration
+ * independent and is sampled without rejection, the rest is the acceptance.  A label is a
+ * pair proposal with probability `pair` (else the single-hop proposal of or_draw):
+ * i and d1 (j = i + d1) and u are the single hop's; the partner offset e (k = i + e) is
+ * uniform over the hop vectors |e| <= rc, and d2 (l = k + d2) follows the tunnelling tower.
+ * A move is proposed with the same probability as its reverse (j -> i, l -> k): e and -e,
+ * d and -d share an orbit, and the labelling with k first has the same probability, so
+ * Metropolis acceptance of the total dH keeps detailed balance with exp(-H/T).  Stream
+ * PAIR at the label gives the words: w0 < pair 2^32 chooses a pair proposal, w1 picks the
+ * orbit of e from the uniform thresholds and w3 & (size - 1) its member, w2 the orbit of
+ * d2 from the tunnelling tower and (w3 >> 3) & (size - 1) its member.  Each single hop
+ * keeps its rate Gamma^T_ij, so labels arrive at the rate Gamma / (1 - pair), and a given
+ * pair move (proposed with probability 2 / (N n_vec) q(d1) q(d2) per pair label, q(d) =
+ * exp(-2|d|/xi) / S, S = sum_d exp(-2|d|/xi), n_vec hop vectors) has
+ * lambda = 2 pair / ((1 - pair) n_vec S).                                        */
+void or_draw_label(const or_state* st, uint64_t s, int32_t* is_pair, int32_t* i, int32_t* v1,
+                   int32_t* ve, int32_t* v2, double* u) {
+  or_draw(st, s, i, v1, u);
+  *is_pair = 0;
+  *ve = -1;
+  *v2 = -1;
+  if (st->thr_pair == 0) return;
+  uint32_t w[4];
+  stream(st, s, TAG_PAIR, w);
+  if (!((uint64_t)w[0] < st->thr_pair)) return;
+  *is_pair = 1;
+  int32_t o = 0;
+  while (!((uint64_t)w[1] < st->thr_u[o])) ++o;
+  *ve = st->orb_first[o] + (int32_t)(w[3] & (uint32_t)(st->orb_size[o] - 1));
+  o = 0;
+  while (!((uint64_t)w[2] < st->thr[o])) ++o;
+  *v2 = st->orb_first[o] + (int32_t)((w[3] >> 3) & (uint32_t)(st->orb_size[o] - 1));
+}
+
+static int32_t shift(const or_state* st, int32_t i, int32_t v) {
+  const int32_t L = st->p.L;
+  return wrap(i / L + st->vec_dy[v], L) * L + wrap(i % L + st->vec_dx[v], L);
+}
+
+static double vsite(const or_state* st, int32_t a, int32_t b) {
+  const int32_t L = st->p.L;
+  return or_invr(st, a % L - b % L, a / L - b / L);
+}
+
+/* Sites of a pair proposal and whether the final sites are within the cutoff. */
+static int pair_sites(const or_state* st, int32_t i, int32_t v1, int32_t ve, int32_t v2, int32_t* j,
+                      int32_t* k, int32_t* l) {
+  const int32_t L = st->p.L;
+  *j = shift(st, i, v1);
+  *k = shift(st, i, ve);
+  *l = shift(st, *k, v2);
+  int32_t dx = wrap(*l % L - *j % L, L), dy = wrap(*l / L - *j / L, L);
+  if (L - dx < dx) dx = L - dx;
+  if (L - dy < dy) dy = L - dy;
+  return (double)(dx * dx + dy * dy) <= st->p.rc * st->p.rc;
+}
+
+/* Filters of a pair proposal: theta_ij theta_kl (i and k occupied, j and l empty), j != l
+ * (the two electrons may not end on one site) and the final sites within the cutoff. */
+static int pair_valid(const or_state* st, int32_t i, int32_t j, int32_t k, int32_t l, int near) {
+  return st->n[i] == 1 && st->n[k] == 1 && st->n[j] == 0 && st->n[l] == 0 && j != l && near;
+}
+
+/* Field-free energy change of the pair move from the energies before it, in this order:
+ * ((eps_j - eps_i) - 1/r_ij) + ((eps_l - eps_k) - 1/r_kl), plus
+ * ((1/r_ik + 1/r_jl) - 1/r_il) - 1/r_jk.  The field term is -E (dx1 + dx2).     */
+static double pair_dh0(const or_state* st, int32_t i, int32_t j, int32_t k, int32_t l, int32_t v1, int32_t v2) {
+  const double* e = st->eps;
+  double h1 = (e[j] - e[i]) - or_invr(st, st->vec_dx[v1], st->vec_dy[v1]);
+  double h2 = (e[l] - e[k]) - or_invr(st, st->vec_dx[v2], st->vec_dy[v2]);
+  double hi = ((vsite(st, i, k) + vsite(st, j, l)) - vsite(st, i, l)) - vsite(st, j, k);
+  return (h1 + h2) + hi;
+}
+
+/* Acceptance probability of a pair proposal in the current configuration (0 when a site
+ * coincides or the occupancy or final-separation filter fails); *dH receives the energy
+ * change when the sites are valid. */
+double or_move_pair(const or_state* st, int32_t i, int32_t v1, int32_t ve, int32_t v2, double* dH) {
+  int32_t j, k, l;
+  int near = pair_sites(st, i, v1, ve, v2, &j, &k, &l);
+  if (dH) *dH = 0.0 / 0.0;
+  if (!pair_valid(st, i, j, k, l, near)) return 0.0;
+  double d = pair_dh0(st, i, j, k, l, v1, v2) - st->p.E * (double)(st->vec_dx[v1] + st->vec_dx[v2]);
+  if (dH) *dH = d;
+  double a = metropolis(st, d);
+  return a > 1.0 ? 1.0 : a;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Step 3b: after hop i -> j, eps_l += 1/r_lj - 1/r_li for every l, with
  * 1/r(0) = 0 giving +1/r_ij at i and -1/r_ij at j.                             */
 static void update_eps(or_state* st, int32_t i, int32_t j) {
@@ -497,20 +613,21 @@ double or_gamma_dt(uint64_t seed, uint32_t sample_id, uint64_t hop, uint64_t m, 
  * clamped at zero, or by the exact Gamma(m, Gamma) time of the serial algorithm.
  * The Gaussian uses Box-Muller on stream CLOCK, index = hop.  */
 static void advance_clock(or_state* st, uint64_t m) {
+  const double G = st->Gamma_lab;
   if (st->p.clock_mode == 0) {
-    st->t = (double)st->s_last / st->Gamma;
+    st->t = (double)st->s_last / G;
     return;
   }
   if (st->p.clock_mode == 2) {
-    st->t = st->t + or_gamma_dt(st->p.seed, st->p.sample_id, st->hops, m, st->Gamma);
+    st->t = st->t + or_gamma_dt(st->p.seed, st->p.sample_id, st->hops, m, G);
     return;
   }
   uint32_t w[4];
   stream(st, st->hops, TAG_CLOCK, w);
   double u1 = unit52(w[0], w[1]), u2 = unit52(w[2], w[3]);
   double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
-  double mean = (double)m / st->Gamma;
-  double sd = sqrt((double)m) / st->Gamma;
+  double mean = (double)m / G;
+  double sd = sqrt((double)m) / G;
   double dt = mean + sd * z;
   if (dt < 0.0) dt = 0.0;
   st->t = st->t + dt;
@@ -559,8 +676,9 @@ int64_t or_naive_run(or_state* st, double t_end) {
 }
 
 int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
-               uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap) {
-  int64_t done = 0, scanned = 0;
+               uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap, int64_t* n_logged) {
+  int64_t done = 0, scanned = 0, logged = 0;
+  if (n_logged) *n_logged = 0;
   if (st->lazy) return -1; /* no energies to run with */
   for (;;) {
     if (n_hops > 0 && done >= n_hops) break;
@@ -570,9 +688,41 @@ int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
     uint64_t s = st->s_scan + 1;
     st->s_scan = s;
     ++scanned;
-    int32_t i, v;
+    int32_t i, v, is_pair, ve, v2;
     double u;
-    or_draw(st, s, &i, &v, &u);
+    or_draw_label(st, s, &is_pair, &i, &v, &ve, &v2, &u);
+    if (is_pair) {
+      /* a pair proposal: filters, then Metropolis on the total dH */
+      int32_t j, k, l;
+      int near = pair_sites(st, i, v, ve, v2, &j, &k, &l);
+      if (!pair_valid(st, i, j, k, l, near)) continue;
+      st->theta_pass++;
+      double dH0 = pair_dh0(st, i, j, k, l, v, v2);
+      double dH = dH0 - st->p.E * (double)(st->vec_dx[v] + st->vec_dx[v2]);
+      if (!(dH <= 0.0 || u < metropolis(st, dH))) continue;
+      st->n[i] = 0;
+      st->n[j] = 1;
+      st->n[k] = 0;
+      st->n[l] = 1;
+      st->P += st->vec_dx[v] + st->vec_dx[v2];
+      st->H0 = st->H0 + dH0;
+      uint64_t m = s - st->s_last;
+      st->s_last = s;
+      st->hops++;
+      for (int e = 0; e < 2; ++e) {
+        if (log_label && logged < log_cap) {
+          log_label[logged] = s;
+          log_i[logged] = e ? k : i;
+          log_j[logged] = e ? l : j;
+          ++logged;
+        }
+      }
+      update_eps(st, i, j);
+      update_eps(st, k, l);
+      advance_clock(st, m);
+      ++done;
+      continue;
+    }
     int32_t j = partner(st, i, v);
     /* step 2: accept with theta_ij min(1, exp(-dH/T)) */
     if (!(st->n[i] == 1 && st->n[j] == 0)) continue;
@@ -588,14 +738,16 @@ int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
     uint64_t m = s - st->s_last;
     st->s_last = s;
     st->hops++;
-    if (log_label && done < log_cap) {
-      log_label[done] = s;
-      log_i[done] = i;
-      log_j[done] = j;
+    if (log_label && logged < log_cap) {
+      log_label[logged] = s;
+      log_i[logged] = i;
+      log_j[logged] = j;
+      ++logged;
     }
     update_eps(st, i, j);
     advance_clock(st, m);
     ++done;
   }
+  if (n_logged) *n_logged = logged;
   return done;
 }

@@ -49,6 +49,8 @@ typedef struct or_params {
   uint32_t sample_id; /* Philox counter word 2 */
   int32_t clock_mode; /* 0: dt = m/Gamma ; 1: Gaussian dt (mean m/Gamma, sd sqrt(m)/Gamma) ;
                          2: exact Gamma(m, Gamma) dt of the serial algorithm */
+  double pair;        /* probability that a label proposes a pair hop, in [0, 1); 0 = the
+                         paper's single-electron model (see or_draw_label) */
 } or_params;
 
 typedef struct or_scalars {
@@ -60,6 +62,7 @@ typedef struct or_scalars {
   double H0;             /* field-free energy, updated by the executed dH */
   uint64_t theta_pass;   /* labels that passed the occupancy filter */
   double Gamma;          /* total proposal rate N * sum_d exp(-2|d|/xi) */
+  double Gamma_lab;      /* label rate Gamma / (1 - pair): the clock's rate */
 } or_scalars;
 
 typedef struct or_state or_state;
@@ -105,10 +108,21 @@ int or_set_occ(or_state* st, const uint8_t* n);
 /* Run the serial chain (not on a lazy state: returns -1) until n_hops more hops have executed, or (t_end >= 0)
  * until the first hop that brings the clock to t >= t_end, or until max_labels
  * more labels were examined (max_labels <= 0: no cap).  Executed hops are
- * logged (label, i, j) while log_cap allows; logs may be NULL.
- * Returns the number of hops executed in this call. */
+ * logged (label, i, j) while log_cap allows (a pair hop logs two entries with its label,
+ * i -> j then k -> l); logs may be NULL, n_logged (may be NULL) receives the entries
+ * written.  Returns the number of hops (single or pair) executed in this call. */
 int64_t or_run(or_state* st, int64_t n_hops, double t_end, int64_t max_labels,
-               uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap);
+               uint64_t* log_label, int32_t* log_i, int32_t* log_j, int64_t log_cap, int64_t* n_logged);
+
+/* Label s of the model with pair hops: the single-hop draw of or_draw (i, v1, u) and,
+ * when stream PAIR makes it a pair proposal (*is_pair = 1), the partner offset vector ve
+ * (k = i + vec[ve]) and the second hop vector v2 (l = k + vec[v2]); else ve = v2 = -1. */
+void or_draw_label(const or_state* st, uint64_t s, int32_t* is_pair, int32_t* i, int32_t* v1,
+                   int32_t* ve, int32_t* v2, double* u);
+/* Acceptance probability of the pair proposal (i, v1, ve, v2) in the current configuration:
+ * theta_ij theta_kl min(1, exp(-dH/T)), 0 when j == l or the final sites are farther apart
+ * than rc; *dH (may be NULL) receives dH when the sites are valid, else NaN. */
+double or_move_pair(const or_state* st, int32_t i, int32_t v1, int32_t ve, int32_t v2, double* dH);
 
 /* Naive serial KMC on the current configuration (uniform pair proposals, acceptance
  * exp(-2 r/xi) theta min(1, exp(-dH/T)) within the cutoff, clock +1 per N (N - 1)

@@ -315,3 +315,164 @@ def check_geometric_m(L=16, T=0.1, E=0.01, M=64, relax=1000, hops=1500, seed=7):
     zm /= math.sqrt(hops)
     zp /= math.sqrt(hops)
     return abs(zm) < 4.0 and abs(zp) < 4.0, f"z(m)={zm:.2f} z(p)={zp:.2f}"
+
+
+# ---------------------------------------------------------------- pair hops
+def _pair_sites(L, t, i, v1, ve, v2):
+    j = _partner(L, i, int(t["dx"][v1]), int(t["dy"][v1]))
+    k = _partner(L, i, int(t["dx"][ve]), int(t["dy"][ve]))
+    l = _partner(L, k, int(t["dx"][v2]), int(t["dy"][v2]))
+    return j, k, l
+
+
+def check_pair_dh_identity(o: oracle.Oracle, n_moves: int = 150, seed: int = 0):
+    """dH of a pair hop i -> j, k -> l equals H(after) - H(before) from Eq. 1, the field term
+    -E (dx1 + dx2) included, for random valid pair moves (brute-force Eq. 1, no use of the
+    oracle's energies)."""
+    L, E = o.L, o.params["E"]
+    t = o.tower()
+    phi = o.phi()
+    rng = np.random.default_rng(seed)
+    n0 = o.occ()
+    H0 = eq1_energy(L, n0, phi)
+    nv = len(t["dx"])
+    worst, tried, attempts = 0.0, 0, 0
+    while tried < n_moves and attempts < 200 * n_moves:
+        attempts += 1
+        i = int(rng.choice(np.flatnonzero(n0 == 1)))
+        v1, ve, v2 = (int(x) for x in rng.integers(nv, size=3))
+        j, k, l = _pair_sites(L, t, i, v1, ve, v2)
+        p, dH = o.move_pair(i, v1, ve, v2)
+        valid = n0[k] == 1 and n0[j] == 0 and n0[l] == 0 and j != l
+        if not valid:
+            if p != 0.0:
+                return False, f"invalid pair move (i={i}, j={j}, k={k}, l={l}) has acceptance {p}"
+            continue
+        if not math.isfinite(dH):  # final sites beyond the cutoff
+            continue
+        n1 = n0.copy()
+        n1[i], n1[j], n1[k], n1[l] = 0, 1, 0, 1
+        want = (eq1_energy(L, n1, phi) - H0) - E * float(t["dx"][v1] + t["dx"][v2])
+        worst = max(worst, abs(dH - want))
+        tried += 1
+    return tried == n_moves and worst < 1e-11, f"max |dH - (H(b)-H(a))| = {worst:.3g} over {tried} pair moves"
+
+
+def check_pair_boltzmann_exact(L: int = 3, n_e: int = 4, rc: float = math.sqrt(2.0), T: float = 0.5,
+                               pair: float = 0.4, seed: int = 5):
+    """Per-proposal transition matrix on a tiny torus at E = 0 when a label is a pair proposal
+    with probability `pair` (site 1/N; partner offset uniform over the hop vectors; hop vectors
+    from the tunnelling tower): pi ~ exp(-H/T) from Eq. 1 must satisfy pi P = pi, which holds
+    only if pair moves are proposed as often as their reverse and accepted by their true
+    energy change.  On the 3x3 torus every two sites are within sqrt 2 of each other; the 4x4
+    torus with rc = 1 also exercises the final-separation filter."""
+    from itertools import combinations
+
+    N = L * L
+    o = oracle.Oracle(L=L, n_e=n_e, W=1.0, rc=rc, T=T, E=0.0, seed=seed, pair=pair)
+    phi = o.phi()
+    t = o.tower()
+    nv = len(t["dx"])
+    states = [tuple(c) for c in combinations(range(N), n_e)]
+    index = {s: k for k, s in enumerate(states)}
+    S = len(states)
+    P = np.zeros((S, S))
+    H = np.zeros(S)
+    qv = np.array([o.vec_prob(v) for v in range(nv)])
+    for a, s in enumerate(states):
+        n = np.zeros(N, np.uint8)
+        n[list(s)] = 1
+        o.set_occ(n)
+        H[a] = eq1_energy(L, n, phi)
+        for i in range(N):
+            for v in range(nv):
+                p, _ = o.move(i, v)
+                if p > 0.0:
+                    j = _partner(L, i, int(t["dx"][v]), int(t["dy"][v]))
+                    m = n.copy()
+                    m[i], m[j] = 0, 1
+                    P[a, index[tuple(np.flatnonzero(m).tolist())]] += (1.0 - pair) / N * qv[v] * p
+            if n[i] == 0:
+                continue
+            for v1 in range(nv):
+                for ve in range(nv):
+                    for v2 in range(nv):
+                        p, _ = o.move_pair(i, v1, ve, v2)
+                        if p == 0.0:
+                            continue
+                        j, k, l = _pair_sites(L, t, i, v1, ve, v2)
+                        m = n.copy()
+                        m[i], m[j], m[k], m[l] = 0, 1, 0, 1
+                        b = index[tuple(np.flatnonzero(m).tolist())]
+                        P[a, b] += pair / N / nv * qv[v1] * qv[v2] * p
+        P[a, a] = 1.0 - (P[a].sum() - P[a, a])
+    pi = np.exp(-(H - H.min()) / T)
+    pi /= pi.sum()
+    res = float(np.abs(pi @ P - pi).max())
+    moves = int((P > 0).sum())
+    return res < 1e-13, f"max |pi P - pi| = {res:.3g} ({moves} nonzero entries)"
+
+
+def check_pair_invariants(o: oracle.Oracle, hops: int):
+    """With pair hops: charge conservation, the log replays (each entry moves an electron to an
+    empty site; a pair hop's two entries share a label), the dipole is the sum of the logged
+    dx, the clock is s_last / Gamma_lab with Gamma_lab = Gamma / (1 - pair), the incremental
+    energies equal the O(N^2) recompute, and pair hops occur."""
+    L = o.L
+    n0 = o.occ()
+    sc0 = o.scalars()
+    lab, li, lj = o.run(hops, max_labels=50_000_000)
+    sc = o.scalars()
+    n = n0.copy()
+    replay, sum_dx = True, 0
+    for a, b in zip(li.tolist(), lj.tolist()):
+        replay &= n[a] == 1 and n[b] == 0
+        n[a], n[b] = 0, 1
+        d = (b % L - a % L) % L
+        sum_dx += d - L if d > L // 2 else d
+    replay &= bool(np.array_equal(n, o.occ()))
+    pairs = int(np.sum(np.diff(lab.astype(np.int64)) == 0))
+    hops_ok = len(lab) - pairs == hops == o.last_run_hops
+    gl = sc["Gamma"] / (1.0 - o.params["pair"])
+    clock = abs(sc["t"] - sc["s_last"] / gl) <= 1e-15 * sc["t"] and sc["Gamma_lab"] == gl
+    dip = sum_dx == sc["P"] - sc0["P"]
+    charge = int(o.occ().sum()) == o.params["n_e"]
+    d = float(np.abs(o.eps() - o.recompute_eps()).max())
+    ok = replay and hops_ok and clock and dip and charge and d < 1e-12 and pairs > 0
+    return ok, (f"replay={replay} hops={hops_ok} clock={clock} dipole={dip} charge={charge} "
+                f"eps drift={d:.3g} pair hops={pairs}")
+
+
+def check_pair_draws(o: oracle.Oracle, xi: float, n: int = 60_000):
+    """Pair labels: their fraction is `pair` (binomial z), the partner offset is uniform over
+    the hop vectors and the second hop vector follows exp(-2|d|/xi) (chi-square each)."""
+    t = o.tower()
+    nv = len(t["dx"])
+    w = np.exp(-2.0 * np.sqrt(t["dx"].astype(float) ** 2 + t["dy"].astype(float) ** 2) / xi)
+    q = w / w.sum()
+    ce = np.zeros(nv)
+    c2 = np.zeros(nv)
+    npair = 0
+    for s in range(1, n + 1):
+        ip, _, _, ve, v2, _ = o.draw_label(s)
+        if ip:
+            npair += 1
+            ce[ve] += 1
+            c2[v2] += 1
+    p = o.params["pair"]
+    zf = (npair - n * p) / math.sqrt(n * p * (1 - p))
+
+    def chi2_z(c, prob):
+        e = npair * prob
+        keep = e >= 20
+        ee = np.append(e[keep], e[~keep].sum())
+        cc = np.append(c[keep], c[~keep].sum())
+        if ee[-1] == 0:
+            ee, cc = ee[:-1], cc[:-1]
+        x2 = float(((cc - ee) ** 2 / ee).sum())
+        dof = len(ee) - 1
+        return (x2 - dof) / math.sqrt(2 * dof)
+
+    ze = chi2_z(ce, np.full(nv, 1.0 / nv))
+    z2 = chi2_z(c2, q)
+    return abs(zf) < 5 and ze < 5 and z2 < 5, f"fraction z={zf:.2f} offset z={ze:.2f} hop z={z2:.2f}"

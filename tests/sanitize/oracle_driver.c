@@ -35,8 +35,8 @@ static int square(int32_t L, int32_t n_e, double rc, double T, double E, int32_t
   uint64_t* lab = malloc(sizeof(uint64_t) * (size_t)hops);
   int32_t* li = malloc(sizeof(int32_t) * (size_t)hops);
   int32_t* lj = malloc(sizeof(int32_t) * (size_t)hops);
-  CHECK(or_run(st, hops, -1.0, 0, lab, li, lj, hops) == hops);
-  CHECK(or_run(st, 5, -1.0, 0, NULL, NULL, NULL, 0) == 5);
+  CHECK(or_run(st, hops, -1.0, 0, lab, li, lj, hops, NULL) == hops);
+  CHECK(or_run(st, 5, -1.0, 0, NULL, NULL, NULL, 0, NULL) == 5);
   double* e = malloc(sizeof(double) * (size_t)N);
   double* e2 = malloc(sizeof(double) * (size_t)N);
   double* phi = malloc(sizeof(double) * (size_t)N);
@@ -62,14 +62,14 @@ static int square(int32_t L, int32_t n_e, double rc, double T, double E, int32_t
   or_get_scalars(st, &sc);
   CHECK(sc.hops == (uint64_t)hops + 5);
   CHECK(or_naive_run(st, sc.t + 1e-3) >= 0);
-  or_run(st, 0, sc.t + 1.0, 0, NULL, NULL, NULL, 0);
+  or_run(st, 0, sc.t + 1.0, 0, NULL, NULL, NULL, 0, NULL);
   n[0] = (uint8_t)(1 - n[0]);
   CHECK(or_set_occ(st, n) != 0); /* wrong electron count */
   or_destroy(st);
   or_state* lz = NULL;
   CHECK(or_create_lazy(&p, &lz) == 0);
   CHECK(isfinite(or_site_eps(lz, 0)));
-  CHECK(or_run(lz, 3, -1.0, 0, NULL, NULL, NULL, 0) < 0);
+  CHECK(or_run(lz, 3, -1.0, 0, NULL, NULL, NULL, 0, NULL) < 0);
   or_destroy(lz);
   free(thr); free(size); free(first); free(vx); free(vy);
   free(lab); free(li); free(lj); free(e); free(e2); free(phi); free(n);
@@ -113,6 +113,31 @@ int main(void) {
   if (square(15, 100, 4.0, 0.1, 0.01, 1, 300)) return 1;
   if (square(16, 128, 6.0, 0.05, 0.0, 2, 300)) return 1;
   if (square(3, 4, 1.0, 0.5, 0.0, 0, 50)) return 1;
+  {
+    /* pair hops: draws, moves and a run */
+    or_params pp = {8, 32, 1.0, 1.0, 3.0, 0.2, 0.05, 4, 3, 0, 0.4};
+    or_state* ps = NULL;
+    CHECK(or_create(&pp, &ps) == 0 && ps);
+    int32_t np_ = 0;
+    for (uint64_t s = 1; s <= 200; ++s) {
+      int32_t ip, i, v1, ve, v2;
+      double u, dH;
+      or_draw_label(ps, s, &ip, &i, &v1, &ve, &v2, &u);
+      if (ip) {
+        ++np_;
+        double a = or_move_pair(ps, i, v1, ve, v2, &dH);
+        CHECK(a >= 0.0 && a <= 1.0);
+      }
+    }
+    CHECK(np_ > 40 && np_ < 120);
+    uint64_t lab[400];
+    int32_t li[400], lj[400];
+    int64_t nl = 0;
+    CHECK(or_run(ps, 200, -1.0, 0, lab, li, lj, 400, &nl) == 200 && nl >= 200);
+    or_destroy(ps);
+    pp.pair = 1.0;
+    CHECK(or_create(&pp, &ps) != 0 && ps == NULL);
+  }
   if (cubic()) return 1;
   CHECK(or_gamma_dt(3, 1, 7, 40, 123.0) > 0.0);
   or_params bad = {16, 128, 1.0, 1.0, 8.0, 0.1, 0.0, 1, 0, 0}; /* rc >= L/2 */

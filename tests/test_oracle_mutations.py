@@ -41,6 +41,25 @@ def _gamma():
     return pins.check_gamma_pairs(o, 16, 1.0, 6.0)
 
 
+def _pair_dh():
+    o = oracle.Oracle(L=8, n_e=32, rc=3.0, T=0.2, E=0.05, seed=9, pair=0.5)
+    return pins.check_pair_dh_identity(o, n_moves=60)
+
+
+def _pair_exact_filter():
+    return pins.check_pair_boltzmann_exact(L=4, n_e=3, rc=1.0, T=0.3, pair=0.5, seed=2)
+
+
+def _pair_invariants():
+    o = oracle.Oracle(L=12, n_e=72, rc=4.0, T=0.3, E=0.01, seed=2, pair=0.4)
+    return pins.check_pair_invariants(o, 1500)
+
+
+def _pair_draws():
+    o = oracle.Oracle(L=16, n_e=128, rc=4.0, seed=3, pair=0.35)
+    return pins.check_pair_draws(o, 1.0, n=30_000)
+
+
 # case -> (what it plants, (original text, planted text), checks expected to catch it)
 CASES = {
     1: ("field term sign flipped in dH",
@@ -83,6 +102,22 @@ CASES = {
          ("      st->eps[l] = st->eps[l] + (a - b);",
           "      st->eps[l] = st->eps[l] + (b - a);"),
          [_incremental]),
+    11: ("pair interaction term with the wrong sign",
+         ("  double hi = ((vsite(st, i, k) + vsite(st, j, l)) - vsite(st, i, l)) - vsite(st, j, k);",
+          "  double hi = ((vsite(st, i, l) + vsite(st, j, k)) - vsite(st, i, k)) - vsite(st, j, l);"),
+         [_pair_dh, _pair_exact_filter]),
+    12: ("pair final-separation filter dropped",
+         ("&& j != l && near;", "&& j != l;"),
+         [_pair_exact_filter]),
+    13: ("second electron of a pair not applied to the energies",
+         ("      update_eps(st, k, l);\n", ""),
+         [_pair_invariants]),
+    14: ("pair dipole counts the first electron only",
+         ("      st->P += st->vec_dx[v] + st->vec_dx[v2];", "      st->P += st->vec_dx[v];"),
+         [_pair_invariants]),
+    15: ("partner offset drawn from the tunnelling tower",
+         ("  while (!((uint64_t)w[1] < st->thr_u[o])) ++o;", "  while (!((uint64_t)w[1] < st->thr[o])) ++o;"),
+         [_pair_draws, _pair_exact_filter]),
 }
 
 
