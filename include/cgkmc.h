@@ -77,6 +77,16 @@ typedef struct cg_sample_desc {
   int32_t dim;       /* lattice: 0 or 2 = square (L^2 sites), 3 = simple cubic (L^3 sites;
                         FP64 form, deterministic clock, 3 <= L <= 24, every sample of the
                         batch cubic); CG_EINVAL otherwise */
+  double pair;       /* probability in [0, 1) that a label proposes a pair hop, two electrons
+                        at once (the multi-electron extension named in sections "Code
+                        performance" and "Conclusions"; rates read as Eq. 2's with the
+                        Eq. 1 energy change of the joint move): i -> j as a single hop and
+                        k -> l with k = i + e, e uniform over the hop vectors, l = k + d2
+                        from the tunnelling tower, both pairs within rc.  0 = the paper's
+                        single-electron model.  pair > 0 in any sample runs the batch on the
+                        pair-hop kernel: square lattices, L <= 128, FP64 form, variant 0 or
+                        1; labels arrive at Gamma / (1 - pair), the clock's rate; a pair
+                        hop logs two entries (i -> j, k -> l) with its label */
 } cg_sample_desc;
 
 typedef struct cg_run_opts {
@@ -259,10 +269,10 @@ int cg_dos(cg_ctx* ctx, int32_t first, int32_t count, double e_lo, double e_hi, 
  * counters; section "Hopping conduction in the Coulomb glass", steps 1-3).
  * cg_save with host_blob == NULL stores the size in *bytes; otherwise *bytes is the buffer
  * size (CG_ENOSPC if too small) and receives the bytes written.  The blob is a header
- * (magic "CGKMCSV1", version 1, precision, the sample's L, n_e, W, xi, rc, seed, sample id
- * and current T and E), the sample state, the occupation words and the energies (8 bytes
+ * (magic "CGKMCSV1", version 2, precision, the sample's L, n_e, W, xi, rc, seed, sample id,
+ * pair probability and current T and E), the sample state, the occupation words and the energies (8 bytes
  * per site: FP64, or the FP32 pair).  cg_load checks the header against sample `sample`
- * of this context (same precision and sample parameters, exact size; CG_EINVAL
+ * of this context (same version, precision and sample parameters, exact size; CG_EINVAL
  * otherwise), restores the state, occupation, energies and T, E, and empties the sample's
  * hop log; the sample then continues exactly as the saved one would have (the labels are
  * counter-based).  The caller owns the blob; both calls synchronise the context stream. */

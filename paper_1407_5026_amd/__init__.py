@@ -40,7 +40,7 @@ EXPORTS = (
 class cg_sample_desc(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_electrons", C.c_int32), ("W", C.c_double), ("xi", C.c_double),
                 ("rc", C.c_double), ("T", C.c_double), ("E", C.c_double), ("seed", C.c_uint64),
-                ("sample_id", C.c_uint32), ("dim", C.c_int32)]
+                ("sample_id", C.c_uint32), ("dim", C.c_int32), ("pair", C.c_double)]
 
 
 class cg_run_opts(C.Structure):
@@ -124,7 +124,8 @@ def _descs(samples):
         d = s if isinstance(s, dict) else s.as_dict()
         arr[k] = cg_sample_desc(int(d["L"]), int(d.get("n_e", d.get("n_electrons"))), float(d["W"]),
                                 float(d["xi"]), float(d["rc"]), float(d["T"]), float(d["E"]),
-                                int(d["seed"]), int(d["sample_id"]), int(d.get("dim", 2)))
+                                int(d["seed"]), int(d["sample_id"]), int(d.get("dim", 2)),
+                                float(d.get("pair", 0.0)))
     return arr
 
 

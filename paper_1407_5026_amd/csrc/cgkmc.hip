@@ -19,6 +19,7 @@
 #include "hop_big.hpp"
 #include "hop_fx.hpp"
 #include "hop_fx64.hpp"
+#include "hop_pair.hpp"
 #include "hop_wide.hpp"
 #include "hop_wide3.hpp"
 #include "kernels.hpp"
@@ -61,6 +62,7 @@ inline size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 struct HostTables {
   int32_t n_orb = 0, n_vec = 0, H = 0;
   std::vector<uint32_t> thr, orb;
+  std::vector<uint32_t> thr_u;    // pair hops: floor(2^32 * cumulative orbit size / n_vec)
   std::vector<int32_t> vec;
   std::vector<uint8_t> guide;
   std::vector<uint16_t> guide16;  // kRaw: orbit | 0x8000 when a threshold lies inside the bucket
@@ -124,6 +126,12 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, int
     t.thr[o] = (uint32_t)(uint64_t)c;
   }
   t.thr[n_orb - 1] = 0xffffffffu;  // never compared: the last orbit takes the rest
+  // uniform law over the n_vec hop vectors by orbit (the partner offset of a pair hop)
+  t.thr_u.assign(n_orb, 0xffffffffu);
+  for (int32_t o = 0; o + 1 < n_orb; ++o) {
+    const uint64_t upto = (uint64_t)(t.orb[o] & 0xffffu) + (uint64_t)(t.orb[o] >> 16) + 1u;
+    t.thr_u[o] = (uint32_t)((upto << 32) / (uint64_t)t.vec.size());
+  }
   t.wsum = acc;
   t.Gamma = (double)N * acc;
   // guide: orbit of the smallest w1 in each bucket of width 2^(32 - kGuideBits)
@@ -242,7 +250,7 @@ int32_t count_vectors(double rc) {
 
 // ---------------------------------------------------------------------------------
 struct SampleLayout {
-  size_t tab64, tabk, thr, orb, vec, guide, vec8, guide16, tdo64, dft_tw, dft_T, static_end;  // uploaded in one copy
+  size_t tab64, tabk, thr, orb, vec, guide, vec8, guide16, tdo64, dft_tw, dft_T, thr_u, static_end;  // uploaded in one copy
   size_t eps, phi, occ, part, log_label, log_from, log_to, mirror, sel, mirror2, occ2, bar, end;
   int32_t dft, dft_kc, dft_rows;
 };
@@ -251,6 +259,7 @@ struct Plan {
   int32_t precision = CG_FP64, block = 1024, U = 1, M = 1024, K = 4096, clock = 0, log_cap = 0, timers = 0;
   int32_t use_graph = 0, variant = 0;
   bool use_db = false, use_fx = false, use_fx64 = false;
+  bool pair = false;  // some sample proposes pair hops: the pair-hop kernel runs the batch
   bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
   bool wide = false; // one sample at a time on G workgroups, each with a replica (variant 6)
   bool coop = false; // hop kernels run as one cooperative launch per sample (big or wide)
@@ -377,8 +386,10 @@ int validate(const cg_sample_desc& d, int32_t b) {
       return set_err(CG_EINVAL, "sample %d: rc=%g must satisfy 1 <= rc < L/2 = %g", b, d.rc, 0.5 * L);
     if (!(d.T > 0.0) || !std::isfinite(d.T)) return set_err(CG_EINVAL, "sample %d: T=%g must be > 0", b, d.T);
     if (!std::isfinite(d.E)) return set_err(CG_EINVAL, "sample %d: E=%g", b, d.E);
+    if (d.pair != 0.0) return set_err(CG_EINVAL, "sample %d: pair hops run on the square lattice only", b);
     return CG_OK;
   }
+  if (!(d.pair >= 0.0) || !(d.pair < 1.0)) return set_err(CG_EINVAL, "sample %d: pair=%g outside [0, 1)", b, d.pair);
   if (L < 3 || (L > 192 && !big_eligible(L)))
     return set_err(CG_EINVAL, "sample %d: L=%d outside [3, 192] and not a power of two in [256, 2048]", b, L);
   const int32_t N = L * L;
@@ -528,6 +539,16 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   int32_t need_db = 0;
   int32_t max_L_all = 0;
   for (int32_t b = 0; b < n; ++b) max_L_all = std::max(max_L_all, s[b].L);
+  for (int32_t b = 0; b < n; ++b) p.pair = p.pair || s[b].pair != 0.0;
+  if (p.pair) {
+    // the pair-hop kernel: the generic FP64 layout (energies in LDS), one label per thread
+    if (p.precision != CG_FP64) return set_err(CG_EINVAL, "pair hops run in the FP64 form");
+    if (p.variant != 0 && p.variant != 1)
+      return set_err(CG_EINVAL, "variant=%d: pair hops run on their own kernel (variant 0 or 1)", p.variant);
+    if (max_L_all > 128) return set_err(CG_EINVAL, "pair hops need every L <= 128 (got %d)", max_L_all);
+    if (p.block != 1024) return set_err(CG_EINVAL, "block=%d: the pair-hop kernel runs 1024 threads", p.block);
+    p.U = 1;
+  }
   p.wide = p.variant == 6;
   if (p.wide) {
     for (int32_t b = 0; b < n; ++b) {
@@ -570,8 +591,10 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     // energy bytes in LDS: FP32 value words (registers hold the pairs), FP64 values in place,
     // none when the batch's largest lattice exceeds 128 (energies stay in the arena)
     const int32_t eb = max_L_all > 128 ? 0 : p.real_bytes;
-    const int32_t f = hop_lds(N, NW, full_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
-    const int32_t t = hop_lds(N, NW, tri_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
+    const int32_t f = p.pair ? pair_lds(N, NW, full_entries(H), n_vec, n_orb).total
+                             : hop_lds(N, NW, full_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
+    const int32_t t = p.pair ? pair_lds(N, NW, tri_entries(H), n_vec, n_orb).total
+                             : hop_lds(N, NW, tri_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
     need_full = std::max(need_full, f);
     need_tri = std::max(need_tri, t);
     full_fits = full_fits && f <= lds_cap;
@@ -591,14 +614,14 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     max_orb = std::max(max_orb, count_orbits(s[b].rc));
   }
   const int32_t need_fx = fx_lds(s[0].L, max_orb, p.block / 64).total;
-  const bool fx_ok = !p.big && p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
+  const bool fx_ok = !p.big && !p.pair && p.precision == CG_FP32_REFRESH && same_L && (s[0].L == 64 || s[0].L == 128) &&
                      need_fx <= lds_cap;
   p.use_fx = fx_ok && (p.variant == 0 || p.variant == 3);
   // exact-geometry FP64 kernel: the same lattices in the FP64 form
   const int32_t need_fx64 = fx64_lds(s[0].L, max_orb).total;
   // (deterministic clock: the stochastic clocks' calls need more registers than the kernel
   // keeps free, and run on the generic kernel; it evaluates chunks of 1024 labels for any M)
-  const bool fx64_ok = !p.big && p.precision == CG_FP64 && same_L && (s[0].L == 64 || s[0].L == 128) &&
+  const bool fx64_ok = !p.big && !p.pair && p.precision == CG_FP64 && same_L && (s[0].L == 64 || s[0].L == 128) &&
                        need_fx64 <= lds_cap && p.block == 1024 && p.clock == CG_CLOCK_DET;
   p.use_fx64 = fx64_ok && (p.variant == 0 || p.variant == 5);
   if (p.variant == 5 && !p.use_fx64)
@@ -686,6 +709,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.tdo64 = off;     off = align_up(off + (bigl ? (size_t)n_orb * 8 : 0));
     q.dft_tw = off;    off = align_up(off + (bigl ? 0 : (size_t)L * 16));
     q.dft_T = off;     off = align_up(off + (bigl ? 0 : (size_t)(H + 1) * L * 8));
+    q.thr_u = off;     off = align_up(off + (size_t)n_orb * 4);
     q.static_end = off;
     q.eps = off;       off = align_up(off + (size_t)N * 8);  // double, or FP32 value + low part
     q.phi = off;       off = align_up(off + (size_t)N * 8);
@@ -808,6 +832,16 @@ HopFn pick_fx_t(int32_t U, int32_t NC, int32_t NW) {
 template <int CLOCK>
 HopFn pick_fx(int32_t U, int32_t NC, int32_t NW, bool timers) {
   return timers ? pick_fx_t<CLOCK, true>(U, NC, NW) : pick_fx_t<CLOCK, false>(U, NC, NW);
+}
+
+// Pair-hop kernel (FP64, L <= 128): geometry from the largest lattice as pick_geo.
+HopFn pick_pair(int32_t layout, int32_t NC, bool exact) {
+  if (layout == kTri) {
+    if (NC == 1) return exact ? k_hops_pair<true, 1, 4, true> : k_hops_pair<true, 1, 4, false>;
+    return exact ? k_hops_pair<true, 2, 8, true> : k_hops_pair<true, 2, 8, false>;
+  }
+  if (NC == 1) return exact ? k_hops_pair<false, 1, 4, true> : k_hops_pair<false, 1, 4, false>;
+  return exact ? k_hops_pair<false, 2, 8, true> : k_hops_pair<false, 2, 8, false>;
 }
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
@@ -1101,7 +1135,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
       return set_err(CG_EHIP, "whole-GPU kernel set-up: %s", hipGetErrorString(e));
     }
   } else {
-    c->hop = pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block, p.timers != 0);
+    c->hop = p.pair ? pick_pair(p.layout, p.NC, p.exact)
+                    : pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block, p.timers != 0);
   }
 
   auto fail = [&](int code) {
@@ -1133,6 +1168,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     else
       std::memcpy(base + q.tabk, t.tabk32.data(), t.tabk32.size() * 4);
     std::memcpy(base + q.thr, t.thr.data(), t.thr.size() * 4);
+    if (!t.thr_u.empty()) std::memcpy(base + q.thr_u, t.thr_u.data(), t.thr_u.size() * 4);
     std::memcpy(base + q.orb, t.orb.data(), t.orb.size() * 4);
     std::memcpy(base + q.vec, t.vec.data(), t.vec.size() * 4);
     std::memcpy(base + q.guide, t.guide.data(), t.guide.size());
@@ -1171,7 +1207,10 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.W = d.W;
     s.T = d.T;
     s.E = d.E;
-    s.Gamma = t.Gamma;
+    // labels arrive at Gamma / (1 - pair): the clock's rate (Gamma itself without pair hops)
+    s.Gamma = t.Gamma / (1.0 - d.pair);
+    s.thr_pair = (uint32_t)(uint64_t)std::floor(std::ldexp(d.pair, 32));
+    s.pair_r2 = (int32_t)std::floor(d.rc * d.rc);
     s.T32 = (float)d.T;
     s.E32 = (float)d.E;
     s.invT32 = (float)(1.0 / d.T);
@@ -1200,6 +1239,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.log_label = (uint64_t*)(a + q.log_label);
     s.log_from = (int32_t*)(a + q.log_from);
     s.log_to = (int32_t*)(a + q.log_to);
+    s.thr_u = (const uint32_t*)(a + q.thr_u);
   }
 #define HIPCHK_C(expr)                                                                     \
   do {                                                                                     \
@@ -1564,8 +1604,11 @@ int cg_get_hop_log(cg_ctx* c, int32_t b, uint64_t* labels, int32_t* from, int32_
   return CG_OK;
 }
 
-int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
-           uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside) {
+namespace {
+
+// Arguments of the density-of-states calls: CG_OK or CG_EINVAL with a message.
+int dos_args(const cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+             const uint64_t* host_occupied, const uint64_t* host_empty, const uint64_t* host_outside) {
   if (!c) return set_err(CG_EINVAL, "null context");
   const int32_t n = (int32_t)c->desc.size();
   if (first < 0 || count < 1 || first + count > n)
@@ -1575,16 +1618,36 @@ int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, in
     return set_err(CG_EINVAL, "energy range [%g, %g)", e_lo, e_hi);
   if (!host_occupied || !host_empty || !host_outside) return set_err(CG_EINVAL, "null output");
   if (count > 65535) return set_err(CG_EINVAL, "count=%d exceeds 65535", count);
+  return CG_OK;
+}
+
+// Clears the 2 nbins + 2 count slots at d_hist and counts samples first .. first + count - 1
+// into them, on the context stream.
+int dos_launch(const cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+               unsigned long long* d_hist) {
   int32_t max_N = 0;
   for (int32_t b = first; b < first + count; ++b) max_N = std::max(max_N, c->dev[b].N);
-  unsigned long long* d_hist = (unsigned long long*)(c->arena + c->plan.hist_off);
   const int slots = 2 * nbins + 2;
+  // a fill kernel, not hipMemsetAsync: the calls may sit inside a captured graph
   hipLaunchKernelGGL(k_fill_u64, dim3((slots + 255) / 256), dim3(256), 0, c->stream, d_hist, slots);
   const double scale = (double)nbins / (e_hi - e_lo);
   const int chunks = (max_N + kDosBlock * kDosSitesPerThread - 1) / (kDosBlock * kDosSitesPerThread);
   hipLaunchKernelGGL(k_dos, dim3(chunks, count), dim3(kDosBlock), 0, c->stream, c->d_samples, first,
                      c->plan.precision == CG_FP64 ? 0 : 1, e_lo, scale, nbins, d_hist);
   HIPCHK(hipGetLastError());
+  return CG_OK;
+}
+
+}  // namespace
+
+int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+           uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside) {
+  int rc = dos_args(c, first, count, e_lo, e_hi, nbins, host_occupied, host_empty, host_outside);
+  if (rc != CG_OK) return rc;
+  unsigned long long* d_hist = (unsigned long long*)(c->arena + c->plan.hist_off);
+  rc = dos_launch(c, first, count, e_lo, e_hi, nbins, d_hist);
+  if (rc != CG_OK) return rc;
+  const int slots = 2 * nbins + 2;
   std::vector<uint64_t> h((size_t)slots);
   HIPCHK(hipMemcpyAsync(h.data(), d_hist, 8 * (size_t)slots, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1604,8 +1667,10 @@ struct SaveHeader {
   uint64_t seed;
   uint32_t sample_id, occ_words;
   uint64_t eps_bytes;
+  double pair;
 };
 constexpr char kSaveMagic[8] = {'C', 'G', 'K', 'M', 'C', 'S', 'V', '1'};
+constexpr uint32_t kSaveVersion = 2;  // 2: the header carries the pair-hop probability
 
 size_t save_bytes(const DevSample& s) { return sizeof(SaveHeader) + sizeof(SampleState) + 4 * (size_t)s.NW + 8 * (size_t)s.N; }
 
@@ -1624,7 +1689,7 @@ int cg_save(cg_ctx* c, int32_t b, void* host_blob, size_t* bytes) {
   SaveHeader h;
   std::memset(&h, 0, sizeof(h));
   std::memcpy(h.magic, kSaveMagic, 8);
-  h.version = 1;
+  h.version = kSaveVersion;
   h.state_bytes = (uint32_t)sizeof(SampleState);
   h.precision = c->plan.precision;
   h.L = d.L;
@@ -1637,6 +1702,7 @@ int cg_save(cg_ctx* c, int32_t b, void* host_blob, size_t* bytes) {
   h.E = d.E;
   h.seed = d.seed;
   h.sample_id = d.sample_id;
+  h.pair = d.pair;
   h.occ_words = (uint32_t)s.NW;
   h.eps_bytes = 8 * (size_t)s.N;
   uint8_t* out = (uint8_t*)host_blob;
@@ -1662,15 +1728,15 @@ int cg_load(cg_ctx* c, int32_t b, const void* host_blob, size_t bytes) {
   SaveHeader h;
   std::memcpy(&h, host_blob, sizeof(h));
   const cg_sample_desc& d = c->desc[b];
-  if (std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1 || h.state_bytes != sizeof(SampleState))
+  if (std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != kSaveVersion || h.state_bytes != sizeof(SampleState))
     return set_err(CG_EINVAL, "not a checkpoint of this library version");
   if (bytes != need || h.occ_words != (uint32_t)s.NW || h.eps_bytes != 8 * (size_t)s.N)
     return set_err(CG_EINVAL, "checkpoint of %zu bytes does not match sample %d (%zu bytes)", bytes, b, need);
   if (h.precision != c->plan.precision)
     return set_err(CG_EINVAL, "checkpoint precision %d, context precision %d", h.precision, c->plan.precision);
   if (h.L != d.L || h.dim != d.dim || h.n_e != d.n_electrons || h.W != d.W || h.xi != d.xi || h.rc != d.rc || h.seed != d.seed ||
-      h.sample_id != d.sample_id)
-    return set_err(CG_EINVAL, "checkpoint is of another sample (L, n_e, W, xi, rc, seed or sample id differ)");
+      h.sample_id != d.sample_id || h.pair != d.pair)
+    return set_err(CG_EINVAL, "checkpoint is of another sample (L, n_e, W, xi, rc, seed, sample id or pair differ)");
   SampleState st;
   const uint8_t* in = (const uint8_t*)host_blob + sizeof(h);
   std::memcpy(&st, in, sizeof(st));

@@ -11,6 +11,7 @@
 //   orb   [n_orb] u32                    first member | (orbit size - 1) << 16
 //   vec   [n_vec] i32                    member displacement (dx & 0xffff) | dy << 16
 //   guide [1024] u8                      orbit at the start of each 2^22-wide bucket of w1
+//   thr_u [n_orb] u32                    cumulative orbit sizes over the hop vectors (pair hops)
 //   dft_tw [L] double2, dft_T [(H+1) L] double   twiddles and transformed 1/r for the refresh
 //   vec8  [n_orb][8] int2, guide16 [1024] u16   proposal tables of the exact-geometry and
 //                                        large-sample kernels; tdo64 [n_orb] double (large)
@@ -92,6 +93,11 @@ struct DevSample {
   uint64_t* log_label;
   int32_t* log_from;
   int32_t* log_to;
+  // pair hops: cumulative orbit sizes (uniform law over the hop vectors, last one unused),
+  // the pair-choice threshold floor(pair 2^32) (0: single hops only) and floor(rc^2)
+  const uint32_t* thr_u;
+  uint32_t thr_pair;
+  int32_t pair_r2;
 };
 
 // Knobs of one hop-kernel launch (uniform over the batch).
@@ -128,6 +134,21 @@ __host__ __device__ inline HopLds hop_lds(int32_t N, int32_t NW, int32_t ntab, i
   o.ctrl = b;  b = align16(b + 96);
   o.info = b;  b = align16(b + 2 * kMaxWaves * kInfoBytes);
   o.total = b;
+  return o;
+}
+
+// LDS of the pair-hop kernel: the generic kernel's FP64 layout and the uniform orbit
+// thresholds of the partner offset.
+struct PairLds {
+  HopLds h;
+  int32_t thr_u, total;
+};
+
+__host__ __device__ inline PairLds pair_lds(int32_t N, int32_t NW, int32_t ntab, int32_t n_vec, int32_t n_orb) {
+  PairLds o;
+  o.h = hop_lds(N, NW, ntab, n_vec, n_orb, 8, 8);
+  o.thr_u = o.h.total;
+  o.total = align16(o.thr_u + n_orb * 4);
   return o;
 }
 

@@ -31,7 +31,8 @@ def oracle_of(s, clock_mode=0):
         return oracle.Oracle3D(L=d["L"], n_e=d["n_e"], W=d["W"], xi=d["xi"], rc=d["rc"], T=d["T"], E=d["E"],
                                seed=d["seed"], sample_id=d["sample_id"])
     return oracle.Oracle(L=d["L"], n_e=d["n_e"], W=d["W"], xi=d["xi"], rc=d["rc"], T=d["T"], E=d["E"],
-                         seed=d["seed"], sample_id=d["sample_id"], clock_mode=clock_mode)
+                         seed=d["seed"], sample_id=d["sample_id"], clock_mode=clock_mode,
+                         pair=d.get("pair", 0.0))
 
 
 def lazy_oracle_of(s):

@@ -72,3 +72,25 @@ def test_arena_bytes_and_validation():
               cg.make_opts(precision=7), cg.make_opts(clock_mode=5), cg.make_opts(phase_timers=3)):
         with pytest.raises(cg.CgError):
             cg.arena_bytes(serial_small(), o)
+
+
+def test_pair_hop_configurations_refused_on_the_host():
+    """Pair hops: square lattices, L <= 128, FP64 form, variant 0 or 1, 0 <= pair < 1."""
+    from workloads import Sample
+
+    ok = Sample(32, 512, 1.0, 1.0, 8.0, 0.06, 0.01, 48, 0, pair=0.2)
+    assert cg.arena_bytes([ok], cg.make_opts(precision=cg.CG_FP64)) > 0
+    bad = [
+        ([ok], cg.make_opts(precision=cg.CG_FP32_REFRESH)),
+        ([ok], cg.make_opts(precision=cg.CG_FP64, variant=5)),
+        ([ok], cg.make_opts(precision=cg.CG_FP64, variant=6)),
+        ([ok], cg.make_opts(precision=cg.CG_FP64, block=512)),
+        ([Sample(256, 32768, 1.0, 1.0, 10.0, 0.05, 0.005, 1, 0, pair=0.1)], cg.make_opts(precision=cg.CG_FP64)),
+        ([Sample(32, 512, 1.0, 1.0, 8.0, 0.06, 0.01, 48, 0, pair=1.0)], cg.make_opts(precision=cg.CG_FP64)),
+        ([Sample(32, 512, 1.0, 1.0, 8.0, 0.06, 0.01, 48, 0, pair=-0.1)], cg.make_opts(precision=cg.CG_FP64)),
+        ([Sample(8, 256, 1.0, 1.0, 2.0, 0.06, 0.01, 48, 0, dim=3, pair=0.1)], cg.make_opts(precision=cg.CG_FP64)),
+    ]
+    for samples, opts in bad:
+        with pytest.raises(cg.CgError) as e:
+            cg.arena_bytes(samples, opts)
+        assert e.value.code == cg.CG_EINVAL

@@ -27,6 +27,7 @@ class Sample:
     seed: int
     sample_id: int
     dim: int = 2  # 2: square lattice (L^2 sites), 3: simple cubic (L^3 sites)
+    pair: float = 0.0  # probability that a label proposes a pair hop (0: single hops only)
 
     def as_dict(self):
         return asdict(self)
