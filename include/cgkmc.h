@@ -263,6 +263,17 @@ int cg_get_hop_log(cg_ctx* ctx, int32_t sample, uint64_t* labels, int32_t* from,
  * context stream; the counts use a scratch region of the arena. */
 int cg_dos(cg_ctx* ctx, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
            uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside);
+/* cg_dos for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same arguments, checks and counts,
+ * but the bin counts live in a file-scope device array of 2 * 4096 + 2 slots (64 KiB + 16
+ * bytes, one copy per device for the life of the process) rather than in the arena, and the
+ * results are copied straight into the caller's host arrays.  It calls no hipMalloc, hipFree
+ * or other allocating routine; the array's device address is resolved by cg_create on the
+ * device current there.  nbins above 4096 is CG_EINVAL.  Every call on one device shares that
+ * device's array and clears it first: calls that overlap on one device (two contexts or two
+ * host threads) race.  Synchronises the context stream. */
+int cg_dos_noalloc(cg_ctx* ctx, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+                   uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside);
 
 /* Checkpoint of one sample (the state the paper's algorithm carries from hop to hop: the
  * occupation of Eq. 1, the local energies of Eq. 2, the clock, the next label and the

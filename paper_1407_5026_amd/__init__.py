@@ -33,7 +33,7 @@ EXPORTS = (
     "cg_arena_bytes", "cg_create", "cg_destroy", "cg_run_hops", "cg_run_time", "cg_refresh",
     "cg_set_TE", "cg_get_occupation", "cg_get_local_energies", "cg_get_phi", "cg_get_stats",
     "cg_get_clock", "cg_get_current", "cg_get_hop_log", "cg_take_kernel_time", "cg_autotune", "cg_last_error",
-    "cg_save", "cg_load", "cg_dos",
+    "cg_save", "cg_load", "cg_dos", "cg_dos_noalloc",
 )
 
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
                                  P(C.c_int64)]
     L.cg_dos.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, P(C.c_uint64),
                          P(C.c_uint64), P(C.c_uint64)]
+    L.cg_dos_noalloc.argtypes = L.cg_dos.argtypes
     L.cg_save.argtypes = [vp, C.c_int32, vp, P(C.c_size_t)]
     L.cg_load.argtypes = [vp, C.c_int32, vp, C.c_size_t]
     L.cg_take_kernel_time.argtypes = [vp, P(C.c_double), P(C.c_int64), P(C.c_double), P(C.c_int64)]
@@ -265,6 +266,17 @@ class Batch:
         u64 = C.POINTER(C.c_uint64)
         _check(load().cg_dos(self._h, first, count, e_lo, e_hi, nbins, occ.ctypes.data_as(u64),
                              emp.ctypes.data_as(u64), out.ctypes.data_as(u64)))
+        return occ, emp, int(out[0]), int(out[1])
+
+    def dos_noalloc(self, first: int, count: int, e_lo: float, e_hi: float, nbins: int):
+        """As dos(), through the allocation-free entry point (counts in the library's
+        file-scope device array; the output arrays are the caller's)."""
+        occ = np.zeros(nbins, np.uint64)
+        emp = np.zeros(nbins, np.uint64)
+        out = np.zeros(2, np.uint64)
+        u64 = C.POINTER(C.c_uint64)
+        _check(load().cg_dos_noalloc(self._h, first, count, e_lo, e_hi, nbins, occ.ctypes.data_as(u64),
+                                     emp.ctypes.data_as(u64), out.ctypes.data_as(u64)))
         return occ, emp, int(out[0]), int(out[1])
 
     def save(self, b: int) -> bytes:

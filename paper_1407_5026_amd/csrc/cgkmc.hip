@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -50,6 +51,39 @@ int set_err(int code, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+// Scratch of the allocation-free density-of-states call: the bin counts of one call
+// (2 kDosMaxBins + 2 slots of 8 bytes, 64 KiB) in a file-scope device array instead of the
+// arena's histogram region.  Every device the library runs on holds its own copy for the
+// life of the process.  In host code the array's name is not a device address: the address
+// comes from hipGetSymbolAddress, resolved once per device with that device current and kept
+// in g_scratch_dev.
+constexpr int kScratchSlots = 2 * kDosMaxBins + 2;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_dev[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned long long scratch[kScratchSlots];
+
+namespace {
+
+// Address of the scratch array on the current device (resolved on the first call per device).
+int scratch_address(unsigned long long** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(CG_EINVAL, "device %d beyond %d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_err(CG_EHIP, "no device address for the scratch array on device %d", dev);
+    g_scratch_dev[dev] = (unsigned long long*)p;
+  }
+  *out = g_scratch_dev[dev];
+  return CG_OK;
+}
 
 // ---------------------------------------------------------------------------------
 // Proposal law of the mixed algorithm on the lattice: displacements d with
@@ -902,6 +936,8 @@ struct cg_ctx {
   double acc_graph_ms = 0.0;
   int64_t n_graph = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_graph;
+  // device address of the file-scope scratch array on the device current at creation
+  unsigned long long* scratch_dev = nullptr;
 };
 
 namespace {
@@ -1103,6 +1139,13 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   c->desc.assign(samples, samples + n);
   c->arena = (uint8_t*)arena;
   c->stream = (hipStream_t)hip_stream;
+  {
+    const int r = scratch_address(&c->scratch_dev);
+    if (r != CG_OK) {
+      delete c;
+      return r;
+    }
+  }
   c->d_samples = (DevSample*)(c->arena + p.samples_off);
   c->d_order = (int32_t*)(c->arena + p.order_off);
   c->d_pending = (int32_t*)(c->arena + p.scratch_off);
@@ -1655,6 +1698,22 @@ int cg_dos(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, in
   std::memcpy(host_empty, h.data() + nbins, 8 * (size_t)nbins);
   host_outside[0] = h[2 * (size_t)nbins];
   host_outside[1] = h[2 * (size_t)nbins + 1];
+  return CG_OK;
+}
+
+int cg_dos_noalloc(cg_ctx* c, int32_t first, int32_t count, double e_lo, double e_hi, int32_t nbins,
+                   uint64_t* host_occupied, uint64_t* host_empty, uint64_t* host_outside) {
+  int rc = dos_args(c, first, count, e_lo, e_hi, nbins, host_occupied, host_empty, host_outside);
+  if (rc != CG_OK) return rc;
+  if (2 * nbins + 2 > kScratchSlots) return set_err(CG_EINVAL, "nbins=%d exceeds the scratch of %d bins", nbins, kDosMaxBins);
+  unsigned long long* d = c->scratch_dev;
+  if (!d) return set_err(CG_EHIP, "scratch array not resolved for this context");
+  rc = dos_launch(c, first, count, e_lo, e_hi, nbins, d);
+  if (rc != CG_OK) return rc;
+  HIPCHK(hipMemcpyAsync(host_occupied, d, 8 * (size_t)nbins, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(host_empty, d + nbins, 8 * (size_t)nbins, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(host_outside, d + 2 * (size_t)nbins, 16, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
   return CG_OK;
 }
 
