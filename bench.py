@@ -303,13 +303,19 @@ def large_lattice(cg, torch, L: int, hops: int, warm: int, T: float, variant: in
 
 def uneven(cg, torch, n: int, t_end: float) -> dict:
     """The uneven batch: n samples with L drawn from {32, 48, 64, 96, 128, 160} and per-sample
-    T, E and W (rc = 10), FP32 form with M and the refresh period autotuned, every sample run
-    from the random start to simulated time t_end.  The batch's largest lattice exceeds 128,
-    so the energies stay in the arena; the samples finish at different hop counts."""
+    T, E and W (rc = 10), FP32 form with the kernel's chunk, the refresh period and each
+    sample's PR width M* = min(1/A, 16384) autotuned, every sample run from the random start to
+    simulated time t_end.  Every lattice's FP32 values fit LDS (L <= 160); the samples finish at
+    different hop counts."""
+    import dataclasses
+
     from workloads import uneven_batch
 
     samples = uneven_batch(n)
-    opts = cg.autotune(samples, cg.make_opts(precision=cg.CG_FP32_REFRESH))
+    t0 = time.perf_counter()
+    opts, widths = cg.autotune(samples, cg.make_opts(precision=cg.CG_FP32_REFRESH), widths=True)
+    tune_s = time.perf_counter() - t0
+    samples = [dataclasses.replace(s, M=w) for s, w in zip(samples, widths)]
     b = cg.Batch(samples, opts)
     torch.cuda.synchronize()
     b.kernel_time()
@@ -321,13 +327,16 @@ def uneven(cg, torch, n: int, t_end: float) -> dict:
     st = [b.stats(k) for k in range(n)]
     b.close()
     hops = sum(x["hops"] for x in st)
-    by_L = {}
+    by_L, M_by_L = {}, {}
     for s, x in zip(samples, st):
         by_L.setdefault(s.L, []).append(x["hops"])
-    return {"samples": n, "t_end": t_end, "M": opts.M, "K_refresh": opts.K_refresh, "hops": hops,
+        M_by_L.setdefault(s.L, []).append(s.M)
+    return {"samples": n, "t_end": t_end, "chunk": opts.M, "K_refresh": opts.K_refresh, "hops": hops,
             "seconds": dt, "hops_per_s": hops / dt, "hop_kernel_ms": hop_ms, "hop_launches": hop_n,
-            "refresh_ms": ref_ms, "max_drift": max(x["max_drift"] for x in st),
-            "mean_hops_by_L": {str(L): round(sum(v) / len(v)) for L, v in sorted(by_L.items())}}
+            "refresh_ms": ref_ms, "max_drift": max(x["max_drift"] for x in st), "autotune_s": tune_s,
+            "mean_hops_by_L": {str(L): round(sum(v) / len(v)) for L, v in sorted(by_L.items())},
+            "M_by_L": {str(L): sorted(set(v)) for L, v in sorted(M_by_L.items())},
+            "mean_p_per_hop": sum(x["sum_p"] for x in st) / max(hops, 1)}
 
 
 def cubic(cg, torch, L: int, batch: int, hops: int, steps: int) -> dict:

@@ -87,6 +87,11 @@ typedef struct cg_sample_desc {
                         pair-hop kernel: square lattices, L <= 128, FP64 form, variant 0 or
                         1; labels arrive at Gamma / (1 - pair), the clock's rate; a pair
                         hop logs two entries (i -> j, k -> l) with its label */
+  int32_t M;         /* parallel width of this sample's PR iterations (section "Parallel
+                        rejection algorithm": a hop found after m serial proposals takes
+                        p = ceil(m / M) iterations, reported in cg_stats.sum_p); a power of two
+                        in [1, 2^24], or 0 for cg_run_opts.M.  The executed hops do not depend on
+                        it: labels past the executed one are re-used */
 } cg_sample_desc;
 
 typedef struct cg_run_opts {
@@ -298,16 +303,21 @@ int cg_load(cg_ctx* ctx, int32_t sample, const void* host_blob, size_t bytes);
 int cg_take_kernel_time(cg_ctx* ctx, double* hop_ms, int64_t* hop_launches, double* refresh_ms,
                         int64_t* refresh_launches);
 
-/* Autotuner of the parallel width (section "Parallel rejection algorithm": the best M is of
- * the order of min(1/A, C), the inverse acceptance or the parallel capacity): chooses opts->M
- * (the kernel's label chunk, 1024 or 2048) by the hop-kernel
- * time of trial runs of trial_hops hops, and, in the FP32 form, opts->K_refresh as the
- * largest of 8192, 4096, 2048, 1024 whose drift over 2K hops from the initial state stays
- * below drift_target / 2 (else 1024).  Each trial creates and destroys a context on
- * `arena` (at least cg_arena_bytes for these samples and options), whose contents are
- * overwritten; no context is left behind.  Runs on hip_stream and synchronises it. */
+/* Autotuner (section "Parallel rejection algorithm": the best parallel width is of the order
+ * of min(1/A, C), the inverse acceptance or the parallel capacity).  Chooses opts->M, the
+ * kernel's label chunk (1024 or 2048), by the hop-kernel time of trial runs of trial_hops
+ * hops; in the FP32 form opts->K_refresh as the largest of 8192, 4096, 2048, 1024 whose drift
+ * over 2K hops from the initial state stays below drift_target / 2 (else 1024); and, when
+ * widths is not NULL, each sample's PR width widths[b] = min(1/A_b, 16384) rounded up to a
+ * power of two and at least 512, with A_b = hops / serial proposals of that sample over the
+ * second half of a trial run of 2 trial_hops hops from its initial state (copy it into the
+ * samples' M).  Each trial creates and destroys a context on `arena` (at least
+ * cg_arena_bytes for these samples and options), whose contents are overwritten; no context
+ * is left behind.  Runs on hip_stream and synchronises it.  CG_EINVAL for trial_hops < 64 or
+ * drift_target <= 0; errors of the trial contexts otherwise. */
 int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, void* arena,
-                size_t arena_bytes, void* hip_stream, int64_t trial_hops, double drift_target);
+                size_t arena_bytes, void* hip_stream, int64_t trial_hops, double drift_target,
+                int32_t* widths);
 
 /* Thread-local description of the last error (empty string if none). */
 const char* cg_last_error(void);

@@ -40,7 +40,7 @@ EXPORTS = (
 class cg_sample_desc(C.Structure):
     _fields_ = [("L", C.c_int32), ("n_electrons", C.c_int32), ("W", C.c_double), ("xi", C.c_double),
                 ("rc", C.c_double), ("T", C.c_double), ("E", C.c_double), ("seed", C.c_uint64),
-                ("sample_id", C.c_uint32), ("dim", C.c_int32), ("pair", C.c_double)]
+                ("sample_id", C.c_uint32), ("dim", C.c_int32), ("pair", C.c_double), ("M", C.c_int32)]
 
 
 class cg_run_opts(C.Structure):
@@ -105,7 +105,7 @@ def load(path: str = LIB_PATH):
     L.cg_load.argtypes = [vp, C.c_int32, vp, C.c_size_t]
     L.cg_take_kernel_time.argtypes = [vp, P(C.c_double), P(C.c_int64), P(C.c_double), P(C.c_int64)]
     L.cg_autotune.argtypes = [P(cg_sample_desc), C.c_int32, P(cg_run_opts), vp, C.c_size_t, vp, C.c_int64,
-                              C.c_double]
+                              C.c_double, P(C.c_int32)]
     L.cg_last_error.restype = C.c_char_p
     for f in EXPORTS:
         if f != "cg_last_error":
@@ -126,7 +126,7 @@ def _descs(samples):
         arr[k] = cg_sample_desc(int(d["L"]), int(d.get("n_e", d.get("n_electrons"))), float(d["W"]),
                                 float(d["xi"]), float(d["rc"]), float(d["T"]), float(d["E"]),
                                 int(d["seed"]), int(d["sample_id"]), int(d.get("dim", 2)),
-                                float(d.get("pair", 0.0)))
+                                float(d.get("pair", 0.0)), int(d.get("M", 0)))
     return arr
 
 
@@ -144,9 +144,10 @@ def arena_bytes(samples, opts: cg_run_opts) -> int:
 
 
 def autotune(samples, opts: cg_run_opts, trial_hops: int = 2048, drift_target: float = 1e-5,
-             device="cuda") -> cg_run_opts:
+             device="cuda", widths: bool = False):
     """Tuned copy of `opts` (chunk width M and, in the FP32 form, refresh period K) from short
-    trial runs of these samples in a scratch arena."""
+    trial runs of these samples in a scratch arena; with widths=True also each sample's PR
+    width min(1/A, 16384) as a power of two >= 512: returns (opts, [M per sample])."""
     import torch
 
     lib = load()
@@ -156,10 +157,11 @@ def autotune(samples, opts: cg_run_opts, trial_hops: int = 2048, drift_target: f
     ptr = (arena.data_ptr() + 255) & ~255
     out = cg_run_opts.from_buffer_copy(opts)
     stream = torch.cuda.current_stream(arena.device)
+    w = (C.c_int32 * len(samples))() if widths else None
     _check(lib.cg_autotune(d, len(samples), C.byref(out), C.c_void_p(ptr), nbytes,
-                           C.c_void_p(stream.cuda_stream), int(trial_hops), float(drift_target)))
+                           C.c_void_p(stream.cuda_stream), int(trial_hops), float(drift_target), w))
     del arena
-    return out
+    return (out, list(w)) if widths else out
 
 
 class Batch:

@@ -294,6 +294,7 @@ struct Plan {
   int32_t use_graph = 0, variant = 0;
   bool use_db = false, use_fx = false, use_fx64 = false;
   bool pair = false;  // some sample proposes pair hops: the pair-hop kernel runs the batch
+  bool split = false;  // FP32, largest L above 128: pairs in the arena, value words in LDS
   bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
   bool wide = false; // one sample at a time on G workgroups, each with a replica (variant 6)
   bool coop = false; // hop kernels run as one cooperative launch per sample (big or wide)
@@ -408,6 +409,8 @@ int build_tables3(const cg_sample_desc& d, HostTables& t) {
 
 int validate(const cg_sample_desc& d, int32_t b) {
   const int32_t L = d.L;
+  if (d.M < 0 || d.M > (1 << 24) || (d.M & (d.M - 1)) != 0)
+    return set_err(CG_EINVAL, "sample %d: M=%d must be 0 or a power of two in [1, 2^24]", b, d.M);
   if (d.dim != 0 && d.dim != 2 && d.dim != 3) return set_err(CG_EINVAL, "sample %d: dim=%d", b, d.dim);
   if (is_cube(d)) {
     if (L < 3 || L > kCubeMaxL) return set_err(CG_EINVAL, "sample %d: cubic L=%d outside [3, %d]", b, L, kCubeMaxL);
@@ -617,6 +620,13 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
                    p.spread);
   }
   int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
+  // FP32 form, largest lattice above 128: the pairs stay in the arena and only their value
+  // words live in LDS (the proposals' random reads), when every sample's fit
+  p.split = p.precision == CG_FP32_REFRESH && max_L_all > 128 && !p.pair && !p.big;
+  for (int32_t b = 0; b < n && p.split; ++b) {
+    const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
+    p.split = hop_lds(N, NW, full_entries(H), count_vectors(s[b].rc), count_orbits(s[b].rc), 4, 4).total <= lds_cap;
+  }
   for (int32_t b = 0; b < n && !p.big; ++b) {
     int rc = validate(s[b], b);
     if (rc != CG_OK) return rc;
@@ -624,7 +634,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     const int32_t n_orb = count_orbits(s[b].rc), n_vec = count_vectors(s[b].rc);
     // energy bytes in LDS: FP32 value words (registers hold the pairs), FP64 values in place,
     // none when the batch's largest lattice exceeds 128 (energies stay in the arena)
-    const int32_t eb = max_L_all > 128 ? 0 : p.real_bytes;
+    const int32_t eb = max_L_all > 128 && !p.split ? 0 : p.real_bytes;
     const int32_t f = p.pair ? pair_lds(N, NW, full_entries(H), n_vec, n_orb).total
                              : hop_lds(N, NW, full_entries(H), n_vec, n_orb, eb, p.real_bytes).total;
     const int32_t t = p.pair ? pair_lds(N, NW, tri_entries(H), n_vec, n_orb).total
@@ -879,7 +889,7 @@ HopFn pick_pair(int32_t layout, int32_t NC, bool exact) {
 }
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
-              int32_t block, bool timers) {
+              int32_t block, bool timers, bool split) {
   if (layout == kCube) {
     switch (NC) {
       case 1: return k_hops3<1>;
@@ -893,6 +903,8 @@ HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool ex
   if (layout == kRaw)
     return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64, timers) : pick_fx<0>(U, NC, block / 64, timers);
   if (db) return pick_db(U, NC, exact);
+  if (NC >= 3 && split)  // FP32, L > 128: pairs in the arena, value words in LDS
+    return U == 1 ? k_hops<float, 1, false, 3, 12, false, kModeSplit> : k_hops<float, 2, false, 3, 12, false, kModeSplit>;
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
     return k_hops<float, 1, false, 3, 12, false, kModeGlobal>;
@@ -979,8 +991,6 @@ int launch_hops(cg_ctx* c, int time_mode) {
     const Plan& p = c->plan;
     RunArgs ra;
     std::memset(&ra, 0, sizeof(ra));
-    ra.M = p.M;
-    while ((1 << ra.log2M) < p.M) ++ra.log2M;
     ra.K = p.K;
     ra.time_mode = time_mode;
     ra.clock_mode = p.clock;
@@ -995,9 +1005,6 @@ int launch_hops(cg_ctx* c, int time_mode) {
   const Plan& p = c->plan;
   RunArgs ra;
   std::memset(&ra, 0, sizeof(ra));
-  ra.M = p.M;
-  ra.log2M = 0;
-  while ((1 << ra.log2M) < p.M) ++ra.log2M;
   ra.K = p.K;
   ra.time_mode = time_mode;
   ra.clock_mode = p.clock;
@@ -1179,7 +1186,8 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     }
   } else {
     c->hop = p.pair ? pick_pair(p.layout, p.NC, p.exact)
-                    : pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block, p.timers != 0);
+                    : pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block, p.timers != 0,
+                               p.split);
   }
 
   auto fail = [&](int code) {
@@ -1242,6 +1250,11 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.dft = q.dft;
     s.dft_kc = q.dft_kc;
     s.dft_rows = q.dft_rows;
+    {
+      const int32_t Mw = d.M ? d.M : p.M;  // the sample's PR width
+      s.log2M = 0;
+      while ((1 << s.log2M) < Mw) ++s.log2M;
+    }
     s.seed_lo = (uint32_t)d.seed;
     s.seed_hi = (uint32_t)(d.seed >> 32);
     s.sample_id = d.sample_id;
@@ -1818,7 +1831,7 @@ int cg_load(cg_ctx* c, int32_t b, const void* host_blob, size_t bytes) {
 }
 
 int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, void* arena, size_t arena_bytes,
-                void* hip_stream, int64_t trial_hops, double drift_target) {
+                void* hip_stream, int64_t trial_hops, double drift_target, int32_t* widths) {
   if (!opts) return set_err(CG_EINVAL, "null options");
   if (trial_hops < 64) return set_err(CG_EINVAL, "trial_hops=%lld must be >= 64", (long long)trial_hops);
   if (!(drift_target > 0.0)) return set_err(CG_EINVAL, "drift_target=%g", drift_target);
@@ -1849,11 +1862,11 @@ int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, voi
     }
   }
   opts->M = best_M;
-  if (opts->precision == CG_FP64) return CG_OK;
   // 2) refresh period: the largest K whose drift over 2K hops from the initial state, where
   //    the energies are widest, stays below half the target
   const int32_t Ks[4] = {8192, 4096, 2048, 1024};
   for (int32_t K : Ks) {
+    if (opts->precision == CG_FP64) break;
     cg_run_opts o = *opts;
     o.K_refresh = K;
     o.log_hops = 0;
@@ -1872,7 +1885,31 @@ int cg_autotune(const cg_sample_desc* samples, int32_t n, cg_run_opts* opts, voi
     cg_destroy(c);
     if (rc != CG_OK) return rc;
     opts->K_refresh = K;
-    if (worst <= 0.5 * drift_target) return CG_OK;
+    if (worst <= 0.5 * drift_target) break;
+  }
+  if (!widths) return CG_OK;
+  // 3) per-sample PR width M* = min(1/A, C): A = hops per serial proposal over the second
+  //    half of a 2 trial_hops run from the initial state, C = 16384; a power of two >= 512
+  cg_run_opts o = *opts;
+  o.log_hops = 0;
+  o.phase_timers = 0;
+  o.use_graph = 0;
+  cg_ctx* c = nullptr;
+  int rc = cg_create(&c, samples, n, &o, arena, arena_bytes, hip_stream);
+  if (rc != CG_OK) return rc;
+  std::vector<cg_stats> st0((size_t)n), st1((size_t)n);
+  rc = cg_run_hops(c, trial_hops);
+  for (int32_t b = 0; b < n && rc == CG_OK; ++b) rc = cg_get_stats(c, b, &st0[b]);
+  if (rc == CG_OK) rc = cg_run_hops(c, trial_hops);
+  for (int32_t b = 0; b < n && rc == CG_OK; ++b) rc = cg_get_stats(c, b, &st1[b]);
+  cg_destroy(c);
+  if (rc != CG_OK) return rc;
+  for (int32_t b = 0; b < n; ++b) {
+    const double props = (double)(st1[b].s_last - st0[b].s_last), hops = (double)(st1[b].hops - st0[b].hops);
+    const double inv_a = hops > 0.0 ? props / hops : 16384.0;
+    int32_t w = 512;
+    while (w < 16384 && (double)w < inv_a) w *= 2;
+    widths[b] = w;
   }
   return CG_OK;
 }

@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
     ++hops;
     P_ += hdx;
     H0 = H0 + dh0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    sum_p += p_iterations(m, S.log2M);
     if (tid == 0) {
       if (lead) {
         // the written copy missed the previous hop of this launch and now takes both, in

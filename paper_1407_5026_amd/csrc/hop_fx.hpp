@@ -85,6 +85,7 @@ struct FxGeo {
 template <typename T>
 using lds_ptr = __attribute__((address_space(3))) T*;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t lds_addr_of(const uint8_t* p) {
   return (uint32_t)(uintptr_t)(lds_ptr<const uint8_t>)p;
@@ -255,6 +256,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   // s / 4 at ev_lane + 1024 (s / 4)
   const uint32_t ev_lane = opaque(lds0 + lo.ev + 4u * (uint32_t)(wid * 64 * SPL + lane * 4));
   constexpr int kRowTab = NW * P * 4;
+  const uint32_t info_lane = opaque(lds0 + lo.info + 16u * (uint32_t)(lane & (kMaxWaves - 1)));
   bool cached = false;
   FxLabel lb[U];
   // the chunk after the current one, drawn during a hop's update (the labels do not depend on
@@ -336,17 +338,17 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     }
     CG_MARK(tc1)
     __syncthreads();
-    // every lane reads a record (lanes l and l + 16 k share one: broadcast reads), only the
-    // first 16 lanes vote
-    const uint4 rec = info[lane & (kMaxWaves - 1)];
+    // every lane reads a whole record in one 16-byte load (lanes l and l + 16 k share one:
+    // broadcast reads), only the first 16 lanes vote; the winner's words are read from its
+    // lane unconditionally (lane 63 when no record carries the tag), so that the record costs
+    // one LDS round trip
+    const u32x4 rec = lds_ld<u32x4>(info_lane);
     const unsigned long long won = __ballot(rec.w == round) & ((1ull << kMaxWaves) - 1ull);
     mk = won != 0ull ? 1u : 0u;
-    if (won != 0ull) {
-      const int wl = __ffsll(won) - 1;
-      win0 = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, wl);
-      win1 = (uint32_t)__builtin_amdgcn_readlane((int)rec.y, wl);
-      win2 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, wl);
-    }
+    const int wl = __ffsll(won | (1ull << 63)) - 1;
+    win0 = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, wl);
+    win1 = (uint32_t)__builtin_amdgcn_readlane((int)rec.y, wl);
+    win2 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, wl);
     ++round;
     if (wid == 0) {  // counters read only at the end, by thread 0
       ++rounds;
@@ -382,7 +384,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     if (wid == 0) {
       P_ += hdx;
       H0 = H0 + (double)dh0;
-      sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+      sum_p += p_iterations(m, S.log2M);
       if (tid == 0) {
         atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
         atomicOr(&occ[hj >> 5], 1u << (hj & 31));

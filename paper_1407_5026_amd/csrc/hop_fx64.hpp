@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
     if (wid == 0) {
       P_ += hdx;
       H0 = H0 + dh0;
-      sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+      sum_p += p_iterations(m, S.log2M);
       if (tid == 0) {
         atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
         atomicOr(&occ[hj >> 5], 1u << (hj & 31));

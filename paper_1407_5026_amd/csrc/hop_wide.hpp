@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
     ++hops;
     P_ += hdx;
     H0 = H0 + dh0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    sum_p += p_iterations(m, S.log2M);
     const bool log_it = logged < log_cap;
     const int64_t log_at = logged;
     logged += log_it ? 1 : 0;

@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops_wide3(const DevSample* __
     ++hops;
     P_ += uni(h.dx);
     H0 = H0 + dh0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    sum_p += p_iterations(m, S.log2M);
     const bool log_it = logged < log_cap;
     const int64_t log_at = logged;
     logged += log_it ? 1 : 0;

@@ -114,6 +114,13 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
 __device__ __forceinline__ int64_t uni(int64_t v) { return (int64_t)uni((uint64_t)v); }
 __device__ __forceinline__ double uni(double v) { return __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(v))); }
 
+// Parallel iterations p = ceil(m / M) of a hop found after m serial proposals, M = 2^l2m the
+// sample's width (section "Parallel rejection algorithm"; the hop itself does not depend on M).
+__device__ __forceinline__ uint64_t p_iterations(uint64_t m, int32_t l2m) {
+  const uint32_t l = (uint32_t)uni(l2m);
+  return (m + ((1ull << l) - 1ull)) >> l;
+}
+
 struct HopInfo {
   uint32_t key;  // position of the label in the chunk: tid * U + k
   int32_t i, j, v;
@@ -269,6 +276,8 @@ enum EnergyMode : int {
   kModeLds = 1,     // energies in LDS, updated in place (FP64: value = storage)
   kModeGlobal = 2,  // energies in the arena (HBM/L2), updated in place; for lattices whose
                     // energies do not fit LDS
+  kModeSplit = 3,   // FP32 pairs in the arena, updated in place by the row update, and their
+                    // value words in LDS for the proposals' random reads
 };
 
 template <typename R, int U, bool TRI, int NC, int RPW, bool EXACT, int MODE>
@@ -304,9 +313,10 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
   const int L = S.L, N = S.N, H1 = S.H + 1, n_orb = S.n_orb;
   const uint32_t magic = S.magic_L;
   extern __shared__ __align__(16) uint8_t smem[];
-  const int32_t eb = MODE == kModeReg ? (int32_t)sizeof(R) : (MODE == kModeLds ? (int32_t)sizeof(ET) : 0);
+  const int32_t eb = (MODE == kModeReg || MODE == kModeSplit) ? (int32_t)sizeof(R)
+                                                                : (MODE == kModeLds ? (int32_t)sizeof(ET) : 0);
   const HopLds lo = hop_lds(N, S.NW, S.ntab, S.n_vec, n_orb, eb, (int32_t)sizeof(R));
-  R* __restrict__ ev = (R*)(smem + lo.eps);  // kModeReg: value words of all energies
+  R* __restrict__ ev = (R*)(smem + lo.eps);  // kModeReg, kModeSplit: value words of all energies
   ET* __restrict__ es = MODE == kModeLds ? (ET*)(smem + lo.eps) : (ET*)S.eps;  // in-place storage
   uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
   R* __restrict__ tab = (R*)(smem + lo.tab);
@@ -338,6 +348,8 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
       }
     } else if constexpr (MODE == kModeLds) {
       for (int k = tid; k < N; k += 1024) es[k] = g[k];
+    } else if constexpr (MODE == kModeSplit) {
+      for (int k = tid; k < N; k += 1024) ev[k] = Energy<R>::value(g[k]);
     }
     const R* gt = (const R*)S.tabk;
     for (int k = tid; k < S.ntab; k += 1024) tab[k] = gt[k];
@@ -398,7 +410,7 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
       const int i = ci[k], j = cj[k];
       const uint32_t wi = occ[i >> 5], wj = occ[j >> 5];
       R ei, ej;
-      if constexpr (MODE == kModeReg) {
+      if constexpr (MODE == kModeReg || MODE == kModeSplit) {
         ei = ev[i];
         ej = ev[j];
       } else {
@@ -475,7 +487,7 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
     ++since;
     P += hdx;
     H0 = H0 + h.dH0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    sum_p += p_iterations(m, S.log2M);
     if (tid == 0) {
       atomicAnd(&occ[h.i >> 5], ~(1u << (h.i & 31)));
       atomicOr(&occ[h.j >> 5], 1u << (h.j & 31));
@@ -543,6 +555,12 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
               E[r][c] = Energy<R>::add(E[r][c], d[rr][c]);
               R* dst = (EXACT || (yv && sto[c] >= 0)) ? ev + (y * L + lane + 64 * c) : (R*)&sh->dummy;
               *dst = Energy<R>::value(E[r][c]);
+            } else if constexpr (MODE == kModeSplit) {
+              if (EXACT || (yv && sto[c] >= 0)) {
+                const ET a = Energy<R>::add(e[rr][c], d[rr][c]);
+                es[y * L + lane + 64 * c] = a;
+                ev[y * L + lane + 64 * c] = Energy<R>::value(a);
+              }
             } else {
               if (EXACT || (yv && sto[c] >= 0)) es[y * L + lane + 64 * c] = Energy<R>::add(e[rr][c], d[rr][c]);
             }
@@ -847,7 +865,7 @@ __global__ void __launch_bounds__(1024) k_hops_db(const DevSample* __restrict__ 
     ++since;
     P += hdx;
     H0 = H0 + hdH0;
-    sum_p += (m + (uint64_t)ra.M - 1) >> ra.log2M;
+    sum_p += p_iterations(m, S.log2M);
     if (tid == 0) {
       atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
       atomicOr(&occ[hj >> 5], 1u << (hj & 31));

@@ -66,7 +66,8 @@ struct DevSample {
   int32_t L, N, H, n_e;
   int32_t NW, n_orb, n_vec, ntab;   // ntab: entries of the hop kernel's table
   int32_t nblk, log_cap, layout, dft;  // dft: refresh by Fourier transform along x
-  int32_t dft_kc, dft_rows, pad2_[2];   // frequencies per LDS chunk, outputs per thread
+  int32_t dft_kc, dft_rows;   // frequencies per LDS chunk, outputs per thread
+  int32_t log2M, pad2_;       // the sample's PR width M = 2^log2M (iterations p = ceil(m / M))
   uint32_t seed_lo, seed_hi, sample_id, magic_L;  // magic_L = ceil(2^32 / L)
   double nu, W, T, E, Gamma;
   float T32, E32, invT32, mTln2_32;  // mTln2_32 = -T ln 2 (acceptance thresholds)
@@ -102,8 +103,6 @@ struct DevSample {
 
 // Knobs of one hop-kernel launch (uniform over the batch).
 struct RunArgs {
-  int32_t M;            // labels per parallel iteration = block * labels_per_lane (power of 2)
-  int32_t log2M;
   int32_t K;            // FP32 form: stop a sample when since_refresh reaches K (0: never)
   int32_t time_mode;    // 1: stop after the hop that brings t >= t_end
   int32_t clock_mode;   // 0: t = s_last / Gamma ; 1: Gaussian increments ; 2: Gamma(m) increments

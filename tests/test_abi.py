@@ -60,8 +60,10 @@ def test_arena_bytes_and_validation():
     big = cg.arena_bytes(headline(256), cg.make_opts(precision=cg.CG_FP32_REFRESH))
     assert big > 256 * 16384 * 4
     cg.arena_bytes(uneven_batch(), cg.make_opts(precision=cg.CG_FP32_REFRESH))
+    assert cg.arena_bytes([dict(serial_small()[0].as_dict(), M=16384)], cg.make_opts()) == n
     bad = dict(serial_small()[0].as_dict())
-    for key, val in (("rc", 8.0), ("T", 0.0), ("L", 2), ("n_e", 0), ("xi", -1.0)):
+    for key, val in (("rc", 8.0), ("T", 0.0), ("L", 2), ("n_e", 0), ("xi", -1.0), ("M", 3), ("M", -2),
+                     ("M", 1 << 25)):
         d = dict(bad)
         d[key] = val
         with pytest.raises(cg.CgError) as e:

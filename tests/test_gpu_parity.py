@@ -79,6 +79,26 @@ def test_trajectory_independent_of_M(M):
     assert st["sum_p"] == int(np.sum((m + M - 1) // M))
 
 
+def test_per_sample_width():
+    """Samples of one batch with their own PR widths (0 = the run options' M): the same hops as
+    the oracle, and each sample's iteration count is its own sum of ceil(m / M_b)."""
+    import dataclasses
+
+    cg = require_gpu()
+    widths = [0, 1, 512, 4096, 16384, 65536]
+    samples = [dataclasses.replace(serial_small(seed=21 + b)[0], sample_id=b, M=w) for b, w in enumerate(widths)]
+    hops = 2000
+    b = _batch(cg, samples, precision=cg.CG_FP64, log_hops=hops, M=2048)
+    b.run_hops(hops)
+    for k, (s, w) in enumerate(zip(samples, widths)):
+        _check_run(cg, b, k, s, oracle_of(s), hops)
+        lab = b.hop_log(k)[0].astype(np.int64)
+        m = np.diff(np.concatenate([[0], lab]))
+        Mk = w or 2048
+        assert b.stats(k)["sum_p"] == int(np.sum((m + Mk - 1) // Mk)), (k, w)
+    say("per-sample widths: iteration counts follow each sample's M")
+
+
 def test_fp64_l64_hop_for_hop():
     cg = require_gpu()
     s = fp64_single()[0]
@@ -158,6 +178,33 @@ def test_uneven_batch_fp32_runs_to_time():
         assert abs(st["t"] - lab[-1] / gamma) <= 1e-12 * st["t"]
         assert int(b.occupation(k).sum()) == s.n_e
         assert st["max_drift"] <= 1e-5, (k, st["max_drift"])
+
+
+def test_uneven_batch_fp32_matches_oracle_until_a_near_tie():
+    """Samples of every size of the uneven batch (L = 32 ... 160, per-sample T, E, W) in one FP32
+    launch, the batch's largest lattice above 128: each executes the oracle's hops until the
+    first label whose FP64 decision FP32 rounding can flip."""
+    cg = require_gpu()
+    from workloads import uneven_batch
+
+    pool = uneven_batch(96)
+    samples = []
+    for s in pool:  # two samples of each size, the batch's order kept
+        if sum(1 for t in samples if t.L == s.L) < 2:
+            samples.append(s)
+    assert {s.L for s in samples} == {32, 48, 64, 96, 128, 160}
+    hops = 1500
+    b = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, K_refresh=512, log_hops=hops)
+    b.run_hops(hops)
+    for k, s in enumerate(samples):
+        o = oracle_of(s)
+        ol = o.run(hops)
+        eps_max = max(float(np.abs(o.eps()).max()), float(np.abs(b.energies(k)).max()))
+        drift = b.stats(k)["max_drift"]
+        agree = compare_logs_fp32(s, b.hop_log(k), ol, drift, eps_max)
+        say(f"uneven FP32 sample {k} (L={s.L}, T={s.T:.3f}): {agree} of {hops} hops identical to the oracle")
+        assert drift <= 1e-5
+        assert int(b.occupation(k).sum()) == s.n_e
 
 
 def test_run_time_matches_oracle():
@@ -324,8 +371,9 @@ def test_graph_replay_matches_eager(prec):
 def test_autotune_returns_valid_choice():
     cg = require_gpu()
     samples = [Sample(64, 2048, 1.0, 1.0, 8.0, 0.05, 0.01, 4, b) for b in range(8)]
-    o = cg.autotune(samples, cg.make_opts(precision=cg.CG_FP32_REFRESH), trial_hops=512)
+    o, widths = cg.autotune(samples, cg.make_opts(precision=cg.CG_FP32_REFRESH), trial_hops=512, widths=True)
     assert o.M in (1024, 2048) and o.K_refresh in (1024, 2048, 4096, 8192)
+    assert all(512 <= w <= 16384 and (w & (w - 1)) == 0 for w in widths), widths
     b = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, M=o.M, K_refresh=o.K_refresh)
     b.run_hops(3000)
     assert max(b.stats(k)["max_drift"] for k in range(len(samples))) <= 1e-5

@@ -28,6 +28,7 @@ class Sample:
     sample_id: int
     dim: int = 2  # 2: square lattice (L^2 sites), 3: simple cubic (L^3 sites)
     pair: float = 0.0  # probability that a label proposes a pair hop (0: single hops only)
+    M: int = 0  # the sample's parallel width (p = ceil(m / M)); 0: the run options' M
 
     def as_dict(self):
         return asdict(self)
