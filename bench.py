@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # LDS bandwidth of the chip: 256 CUs x 224 B/clk x 2.4 GHz, the best rate the unit probe
-# (python -m paper_1407_5026_amd.probe) measures on MI355X, with 16-byte ds_read_b128; 4-byte
+# (paper_1407_5026_amd/csrc/lds_probe.hip) measures on MI355X, with 16-byte ds_read_b128; 4-byte
 # reads reach 65 B/clk (each LDS read instruction occupies the CU's LDS pipe for ~4-5 cycles
 # whatever its width), and writes at most ~72 B/clk at any width
 LDS_PEAK_GBS = 256 * 224 * 2.4

@@ -755,7 +755,9 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.dft_T = off;     off = align_up(off + (bigl ? 0 : (size_t)(H + 1) * L * 8));
     q.thr_u = off;     off = align_up(off + (size_t)n_orb * 4);
     q.static_end = off;
-    q.eps = off;       off = align_up(off + (size_t)N * 8);  // double, or FP32 value + low part
+    // double, or FP32 value + low part; then one 8-byte sink word that the arena-energy hop
+    // kernels write in place of the sites beyond L of lanes past the lattice's edge
+    q.eps = off;       off = align_up(off + (size_t)N * 8 + 8);
     q.phi = off;       off = align_up(off + (size_t)N * 8);
     q.occ = off;       off = align_up(off + (size_t)NW * 4);
     q.part = off;      off = align_up(off + (size_t)2 * nblk * 8);

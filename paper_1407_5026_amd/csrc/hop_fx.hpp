@@ -98,12 +98,6 @@ template <typename T>
 __device__ __forceinline__ void lds_st(uint32_t a, T v) {
   *(lds_ptr<T>)a = v;
 }
-// Keeps a per-lane address opaque so that constant offsets added to it are not merged
-// into a wave-uniform part of its computation.
-__device__ __forceinline__ uint32_t opaque(uint32_t a) {
-  asm volatile("" : "+v"(a));
-  return a;
-}
 
 // Folded column distance min(|x - x0|, L - |x - x0|) for x, x0 in [0, L), L a power of two.
 template <int L>
@@ -133,25 +127,40 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C
   const uint32_t ev = lds0 + lo.ev;
   const int last = C.last;
   const float Ef = C.Ef, mTln2 = C.mTln2;
+  // the Philox words of every label first (pure VALU, no LDS access), then the table lookups
+  // of all of them: the lane waits for LDS once per lookup stage, not once per label
+  uint32_t w0[U], w1[U], w2[U], w3[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {
     const uint64_t lab = base + 1 + (uint64_t)(tid * U + k);
-    uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = C.sid, c3 = kTagPropose;
-    philox10(c0, c1, c2, c3, C.k0, C.k1);
-    const int i = (int)(c0 >> (32 - 2 * G::LG));
-    const uint32_t g = lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuideBits)));
-    int o = (int)(g & 0x7fffu);
-    if (g & 0x8000u) {
-      while (o < last && c1 >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
+    w0[k] = (uint32_t)lab;
+    w1[k] = (uint32_t)(lab >> 32);
+    w2[k] = C.sid;
+    w3[k] = kTagPropose;
+    philox10(w0[k], w1[k], w2[k], w3[k], C.k0, C.k1);
+  }
+  uint32_t g[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) g[k] = lds_ld<uint16_t>(guide + 2 * (w1[k] >> (32 - kGuideBits)));
+  uint64_t v[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    int o = (int)(g[k] & 0x7fffu);
+    if (g[k] & 0x8000u) {
+      while (o < last && w1[k] >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
     }
-    const uint64_t v = lds_ld<uint64_t>(vec8 + 8 * (o * 8 + (int)(c3 & 7u)));
-    const int vx = (int)(uint32_t)v;
+    v[k] = lds_ld<uint64_t>(vec8 + 8 * (o * 8 + (int)(w3[k] & 7u)));
+  }
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const int i = (int)(w0[k] >> (32 - 2 * G::LG));
+    const int vx = (int)(uint32_t)v[k];
     const int dx = (int)(int16_t)(vx & 0xffff), dy = vx >> 16;
     const int xi = i & (L - 1), yi = i >> G::LG;
     const int xj = (xi + dx) & (L - 1), yj = (yi + dy) & (L - 1);
     const int j = (yj << G::LG) | xj;
-    const float td = __uint_as_float((uint32_t)(v >> 32));
-    const float u = (float)(2u * (c2 >> 9) + 1u) * 0x1p-24f;
+    const float td = __uint_as_float((uint32_t)(v[k] >> 32));
+    const float u = (float)(2u * (w2[k] >> 9) + 1u) * 0x1p-24f;
     FxLabel& b = lb[k];
     b.i = i;
     b.j = j;
@@ -192,6 +201,17 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
                       (ra.K > 0 && since >= ra.K);
     if (idle) return;
   }
+  // hops this launch may still execute: up to the call's target and to the next refresh
+  // (launch-local 32-bit counters keep 64-bit scalar arithmetic out of the hop loop)
+  const uint64_t hops0 = hops;
+  uint32_t hleft;
+  {
+    const uint64_t lim_t = target - hops0;
+    const uint64_t lim_k = ra.K > 0 ? (uint64_t)(ra.K - since) : ~0ull;
+    const uint64_t lim = lim_t < lim_k ? lim_t : lim_k;
+    hleft = uni((uint32_t)(lim < 0xffffffffull ? lim : 0xffffffffull));
+  }
+  uint32_t hcnt = (uint32_t)hops0;  // low bits of the hop count (the renormalisation phase)
   uint64_t base = uni(gs->s_scan);  // labels base + 1 .. base + M form the current chunk
   uint32_t dpos = 0;                // labels up to base + dpos are decided
   int64_t P_ = uni(gs->P);
@@ -247,6 +267,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   C.Ef = __uint_as_float(uni(__float_as_uint(S.E32)));
   C.mTln2 = __uint_as_float(uni(__float_as_uint(S.mTln2_32)));
   const double Gamma = uni(S.Gamma);
+  const int32_t l2m = uni(S.log2M);  // the sample's PR width 2^l2m
   const int64_t log_cap = uni((int64_t)S.log_cap);
   uint64_t* __restrict__ log_label = S.log_label;
   int32_t* __restrict__ log_from = S.log_from;
@@ -260,9 +281,9 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   bool cached = false;
   FxLabel lb[U];
   // the chunk after the current one, drawn during a hop's update (the labels do not depend on
-  // the configuration): valid when next_base == base + M
+  // the configuration): lbn holds chunk base + M when pre is set
   FxLabel lbn[U];
-  uint64_t next_base = ~0ull;
+  bool pre = false;
   uint32_t theta_cnt = 0;
   uint32_t round = 0;  // tag of the current evaluation round
   uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
@@ -281,9 +302,10 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     uint32_t mk = 0u, win0 = 0u, win1 = 0u, win2 = 0u;
     for (;;) {
     if (!cached) {
-      if (next_base == base) {
+      if (pre) {
 #pragma unroll
         for (int k = 0; k < U; ++k) lb[k] = lbn[k];
+        pre = false;
       } else {
         draw_fx<L, U, NW>(base, tid, C, lds0, lo, lb);
       }
@@ -292,18 +314,25 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     }
 
     // step 2 for the undecided labels: occupancy filter and Metropolis; the lane keeps its
-    // first accepted label
-    int first = U;
+    // first accepted label (selects, no divergent blocks: the exec mask stays whole)
+    // (0/1 integers in vector registers rather than lane masks: the decision costs vector
+    // instructions only, none of the workgroup's shared scalar unit)
+    uint32_t found = 0u;
     uint32_t pub0 = 0u, pub1 = 0u;
     float pdh = 0.f;
     // the value words of every undecided label are read at once (an accepted label makes the
     // lane's later labels moot, but waiting for its decision would add an LDS round trip)
+    // (a lane with any undecided label reads all of its labels' words: one branch per round;
+    // the words of its decided labels are ignored below)
     uint32_t wis[U], wjs[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       wis[k] = 0u;
       wjs[k] = 0u;
-      if ((uint32_t)(tid * U + k) >= dpos) {
+    }
+    if ((uint32_t)(tid * U + U - 1) >= dpos) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
         wis[k] = lds_ld<uint32_t>(lb[k].ai);
         wjs[k] = lds_ld<uint32_t>(lb[k].aj);
       }
@@ -312,18 +341,20 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     for (int k = 0; k < U; ++k) {
       const FxLabel& b = lb[k];
       const uint32_t key = (uint32_t)(tid * U + k);
-      const bool open = (first == U) & (key >= dpos);  // not yet decided
-      const uint32_t wi = open ? wis[k] : 0u, wj = open ? wjs[k] : 0u;
+      // not yet decided: key >= dpos (both below 2^31) and no earlier label of the lane accepted
+      const uint32_t open = (((key - dpos) >> 31) ^ 1u) & (found ^ 1u);
+      const uint32_t wi = wis[k], wj = wjs[k];
       const float de = __uint_as_float(wj) - __uint_as_float(wi);
-      const bool th = open & ((wi & ~wj & 1u) != 0u);  // n_i (1 - n_j) from the value words
-      const bool acc = th & (de <= b.th);
-      theta_cnt += th ? 1u : 0u;
-      if (acc) {
-        first = k;
-        pub0 = (uint32_t)b.i | ((uint32_t)b.j << 16);
-        pub1 = key | ((uint32_t)b.dx << 16);
-        pdh = de - b.td;
-      }
+      const uint32_t th = open & wi & ~wj & 1u;  // n_i (1 - n_j) from the value words
+      // de <= th exactly when th - de >= 0: the difference of two FP32 values of like size is
+      // exact (Sterbenz), so its sign bit decides
+      const uint32_t le = (__float_as_uint(b.th - de) >> 31) ^ 1u;
+      const uint32_t acc = th & le;
+      theta_cnt += th;
+      pub0 = acc ? ((uint32_t)b.i | ((uint32_t)b.j << 16)) : pub0;
+      pub1 = acc ? (key | ((uint32_t)b.dx << 16)) : pub1;
+      pdh = acc ? de - b.td : pdh;
+      found |= acc;
     }
     // the wave's lowest accepting lane publishes its label in the wave's record, tagged with
     // the round; after the barrier lanes 0..15 read the 16 records (waves beyond NW never
@@ -332,7 +363,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     // index).  A record is rewritten only by its own wave: in a later round, which only
     // happens before another wave reads it for this round if this round executed no hop
     // from that wave, and then the later tag is simply not this round's.
-    const unsigned long long bal = __ballot(first < U);
+    const unsigned long long bal = __ballot(found != 0u);
     if (bal != 0ull) {
       if (lane == __ffsll(bal) - 1) info[wid] = make_uint4(pub0, pub1, __float_as_uint(pdh), round);
     }
@@ -373,18 +404,18 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     const int hi = (int)(w0 & 0xffffu), hj = (int)(w0 >> 16);
     const uint32_t key = w1 & 0xffffu;
     const int hdx = (int)w1 >> 16;
-    const uint64_t q = base + 1 + key;
-    const uint64_t m = q - s_last;
-    s_last = q;
     dpos = key + 1;
-    ++hops;
-    ++since;
+    ++hcnt;
+    --hleft;
     // the state written back at the end (by thread 0): kept by wave 0 only, so that the
     // other waves' scalar work after the barrier is just what their update needs
     if (wid == 0) {
+      const uint64_t q = base + 1 + key;
+      const uint64_t m = q - s_last;
+      s_last = q;
       P_ += hdx;
       H0 = H0 + (double)dh0;
-      sum_p += p_iterations(m, S.log2M);
+      sum_p += p_iterations(m, l2m);
       if (tid == 0) {
         atomicAnd(&occ[hi >> 5], ~(1u << (hi & 31)));
         atomicOr(&occ[hj >> 5], 1u << (hj & 31));
@@ -393,7 +424,9 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
           log_from[logged] = hi;
           log_to[logged] = hj;
         }
-        if (CLOCK != 0) sh->t = sh->t + clock_dt(ra.clock_mode, hops, m, C.sid, C.k0, C.k1, Gamma);
+        if (CLOCK != 0)
+          sh->t = sh->t + clock_dt(ra.clock_mode, hops0 + (uint32_t)(hcnt - (uint32_t)hops0), m, C.sid, C.k0, C.k1,
+                                   Gamma);
       }
       logged += logged < log_cap ? 1 : 0;
     }
@@ -416,11 +449,12 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     CG_SLOT(21) CG_SLOT(22) CG_SLOT(23) CG_SLOT(24) CG_SLOT(25) CG_SLOT(26) CG_SLOT(27) \
     CG_SLOT(28) CG_SLOT(29) CG_SLOT(30) CG_SLOT(31) default: break;                  \
   }
-      if (wid == (yi & (NW - 1)) && lane == (xi & 63)) {
+      // the owner thread of a site is (y % NW) 64 + (x & 63): one vector compare each
+      if (tid == (((yi & (NW - 1)) << 6) | (xi & 63))) {
         const uint32_t n = 0u;
         CG_SLOTS((yi >> G::LW) * NC + (xi >> 6))
       }
-      if (wid == (yj & (NW - 1)) && lane == (xj & 63)) {
+      if (tid == (((yj & (NW - 1)) << 6) | (xj & 63))) {
         const uint32_t n = 1u;
         CG_SLOTS((yj >> G::LW) * NC + (xj >> 6))
       }
@@ -451,9 +485,9 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
           d[r][c] = lds_ld<float>(aj[c] + r * kRowTab) - lds_ld<float>(ai[c] + r * kRowTab);
       }
       // while the table loads are in flight: draw the next chunk if it is not drawn yet
-      if (next_base != base + M) {
-        next_base = base + M;
-        draw_fx<L, U, NW>(next_base, tid, C, lds0, lo, lbn);
+      if (!pre) {
+        pre = true;
+        draw_fx<L, U, NW>(base + M, tid, C, lds0, lo, lbn);
       }
       float v[SPL];
 #pragma unroll
@@ -473,7 +507,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
         w.w = v[4 * q + 3];
         lds_st<f32x4>(ev_lane + 1024 * q, w);
       }
-      if ((hops & (uint64_t)(kRenorm - 1)) == 0) {
+      if ((hcnt & (uint32_t)(kRenorm - 1)) == 0) {
         // Fast2Sum: z = fl(hi + lo) - hi is exact and hi + z = fl(hi + lo), so the pair
         // keeps its sum while hi absorbs lo (written as updates of hi and lo in place); the
         // occupation bit is then put back into hi
@@ -497,12 +531,13 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
       dpos = 0;
       cached = false;
     }
-    if (hops >= target) break;
+    if (hleft == 0u) break;
     if (ra.time_mode) {
-      if (CLOCK == 0 ? s_last >= s_end : uni(sh->t) >= t_end) break;
+      if (CLOCK == 0 ? base + dpos >= s_end : uni(sh->t) >= t_end) break;
     }
-    if (ra.K > 0 && since >= ra.K) break;
   }
+  hops = hops0 + (uint32_t)(hcnt - (uint32_t)hops0);
+  since += (int32_t)(uint32_t)(hops - hops0);
 
   atomicAdd(&sh->theta, theta_cnt);
   {

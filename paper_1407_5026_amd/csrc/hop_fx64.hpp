@@ -201,37 +201,37 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
         }
         cached = true;
       }
-      // step 2: occupancy filter, dH, Metropolis; the lane keeps its first accepted label
-      int first = U;
+      // step 2: occupancy filter, dH, Metropolis; the lane keeps its first accepted label.
+      // The flags are 0/1 integers in vector registers and the thermal factor is evaluated
+      // for every lane (nearly every wave needs it anyway), so the decision uses none of
+      // the workgroup's shared scalar unit for lane masks or divergent branches.
+      uint32_t found = 0u;
       uint32_t pub0 = 0u, pub1 = 0u;
       double pdh = 0.0;
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const Fx64Label& b = lb[k];
         const uint32_t key = (uint32_t)(tid * U + k);
-        const bool open = (first == U) & (key >= dpos);
+        const uint32_t open = (((key - dpos) >> 31) ^ 1u) & (found ^ 1u);
         const int bi = (int)(b.ij & 0xffffu), bj = (int)(b.ij >> 16), bdx = (int)b.aidx >> 24;
         const uint32_t wi = occ[bi >> 5], wj = occ[bj >> 5];
         const double ei = lds_ld<double>(b.aidx & 0xffffffu), ej = lds_ld<double>(b.aj);
-        const bool th = open & ((((wi >> (bi & 31)) & ~(wj >> (bj & 31))) & 1u) != 0u);
+        const uint32_t th = open & (wi >> (bi & 31)) & ~(wj >> (bj & 31)) & 1u;
         const double dh0 = (ej - ei) - b.td;
         const double dH = dh0 - Ed * (double)bdx;
-        bool acc = dH <= 0.0;
-        if (th && !acc) acc = b.u < exp(-dH / T);
-        acc = acc & th;
-        theta_cnt += th ? 1u : 0u;
-        if (acc) {
-          first = k;
-          pub0 = b.ij;
-          pub1 = key | ((uint32_t)bdx << 16);
-          pdh = dh0;
-        }
+        const double pth = exp(-dH / T);
+        const uint32_t acc = th & ((dH <= 0.0) | (b.u < pth) ? 1u : 0u);
+        theta_cnt += th;
+        pub0 = acc ? b.ij : pub0;
+        pub1 = acc ? (key | ((uint32_t)bdx << 16)) : pub1;
+        pdh = acc ? dh0 : pdh;
+        found |= acc;
       }
       // the wave's lowest accepting lane publishes its label in the wave's record, tagged
       // with the round; after the barrier lanes 0..15 read the records and the winner is
       // the lowest wave whose tag is this round's (keys grow with the thread index); a
       // record is rewritten only by its own wave in a later round
-      const unsigned long long bal = __ballot(first < U);
+      const unsigned long long bal = __ballot(found != 0u);
       if (bal != 0ull && lane == __ffsll(bal) - 1) {
         const uint64_t bits = (uint64_t)__double_as_longlong(pdh);
         info[wid] = make_uint4(pub0, pub1, (uint32_t)bits, (uint32_t)(bits >> 32));

@@ -134,6 +134,44 @@ static_assert(sizeof(HopInfo) == kInfoBytes, "HopInfo size");
 // Kahan's compensated summation, so that the pair tracks the exact running sum of the FP32
 // increments and the value word -- the FP32 energy every proposal reads -- stays within
 // about one rounding of it between refreshes.
+// Keeps a per-lane value opaque to the optimizer: constant offsets added to an address are
+// not merged into a wave-uniform part of its computation, and the value is formed where it
+// is written (not hoisted out of a loop).
+__device__ __forceinline__ uint32_t opaque(uint32_t a) {
+  asm volatile("" : "+v"(a));
+  return a;
+}
+
+// Energies in the arena addressed through the global address space: the compiler then
+// knows an access cannot alias the LDS words written beside it and keeps several in flight
+// (a generic pointer makes it wait for every access before the next LDS store).
+// Addresses are a uniform base plus a 32-bit byte offset per lane (the load's scalar-base
+// form: no 64-bit vector address per site).
+template <typename T>
+using gbl_ptr = __attribute__((address_space(1))) T*;
+template <typename ET, typename R>
+__device__ __forceinline__ ET gload(gbl_ptr<R> p, uint32_t byte_off) {
+  const gbl_ptr<R> q = (gbl_ptr<R>)((__attribute__((address_space(1))) char*)p + byte_off);
+  if constexpr (sizeof(ET) == 2 * sizeof(R)) {
+    ET e;
+    e.x = q[0];
+    e.y = q[1];
+    return e;
+  } else {
+    return q[0];
+  }
+}
+template <typename ET, typename R>
+__device__ __forceinline__ void gstore(gbl_ptr<R> p, uint32_t byte_off, ET e) {
+  const gbl_ptr<R> q = (gbl_ptr<R>)((__attribute__((address_space(1))) char*)p + byte_off);
+  if constexpr (sizeof(ET) == 2 * sizeof(R)) {
+    q[0] = e.x;
+    q[1] = e.y;
+  } else {
+    q[0] = e;
+  }
+}
+
 template <typename R> struct Energy;
 template <> struct Energy<double> {
   using T = double;
@@ -318,6 +356,7 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
   const HopLds lo = hop_lds(N, S.NW, S.ntab, S.n_vec, n_orb, eb, (int32_t)sizeof(R));
   R* __restrict__ ev = (R*)(smem + lo.eps);  // kModeReg, kModeSplit: value words of all energies
   ET* __restrict__ es = MODE == kModeLds ? (ET*)(smem + lo.eps) : (ET*)S.eps;  // in-place storage
+  const gbl_ptr<R> eg = (gbl_ptr<R>)S.eps;  // the same storage in the arena modes
   uint32_t* __restrict__ occ = (uint32_t*)(smem + lo.occ);
   R* __restrict__ tab = (R*)(smem + lo.tab);
   int32_t* __restrict__ vec = (int32_t*)(smem + lo.vec);
@@ -413,6 +452,9 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
       if constexpr (MODE == kModeReg || MODE == kModeSplit) {
         ei = ev[i];
         ej = ev[j];
+      } else if constexpr (MODE == kModeGlobal) {
+        ei = Energy<R>::value(gload<ET, R>(eg, (uint32_t)i * (uint32_t)sizeof(ET)));
+        ej = Energy<R>::value(gload<ET, R>(eg, (uint32_t)j * (uint32_t)sizeof(ET)));
       } else {
         ei = Energy<R>::value(es[i]);
         ej = Energy<R>::value(es[j]);
@@ -518,8 +560,20 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         tix[c] = TRI ? tri_of<TRI>(cix[c]) : 0;
         sto[c] = xv ? x : -1;
       }
+      // arena modes: byte offset of the lane's site in column block c and its first row, and
+      // the stride to its next row; a lane beyond the lattice's edge reads and writes the
+      // sample's sink word (after the N energies) instead, so no access needs a lane branch.
+      // Formed here, not hoisted out of the hop loop (one address per site would occupy
+      // registers for the whole launch).
+      uint32_t gco[NC], grs[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const bool xv = sto[c] >= 0;
+        gco[c] = opaque(xv ? (uint32_t)((wid * L + lane + 64 * c) * (int)sizeof(ET)) : (uint32_t)(N * (int)sizeof(ET)));
+        grs[c] = xv ? (uint32_t)(NW * L * (int)sizeof(ET)) : 0u;
+      }
       // rows in groups of RG: every load of a group is issued before its first use
-      constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : 4;
+      constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : (MODE == kModeGlobal || MODE == kModeSplit) ? 2 : 4;
 #pragma unroll
       for (int r0 = 0; r0 < RPW; r0 += RG) {
         R d[RG][NC];
@@ -540,8 +594,11 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
               ki = ayi * H1 + cix[c];
             }
             d[rr][c] = tab[kj] - tab[ki];
-            if constexpr (MODE != kModeReg)
+            if constexpr (MODE == kModeLds) {
               if (EXACT || (yv && sto[c] >= 0)) e[rr][c] = es[y * L + lane + 64 * c];
+            } else if constexpr (MODE != kModeReg) {
+              if (EXACT || yv) e[rr][c] = gload<ET, R>(eg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
+            }
           }
         }
 #pragma unroll
@@ -556,11 +613,14 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
               R* dst = (EXACT || (yv && sto[c] >= 0)) ? ev + (y * L + lane + 64 * c) : (R*)&sh->dummy;
               *dst = Energy<R>::value(E[r][c]);
             } else if constexpr (MODE == kModeSplit) {
-              if (EXACT || (yv && sto[c] >= 0)) {
+              if (EXACT || yv) {
                 const ET a = Energy<R>::add(e[rr][c], d[rr][c]);
-                es[y * L + lane + 64 * c] = a;
-                ev[y * L + lane + 64 * c] = Energy<R>::value(a);
+                gstore<ET, R>(eg, gco[c] + (uint32_t)r * grs[c], a);
+                R* dst = (EXACT || sto[c] >= 0) ? ev + (y * L + lane + 64 * c) : (R*)&sh->dummy;
+                *dst = Energy<R>::value(a);
               }
+            } else if constexpr (MODE == kModeGlobal) {
+              if (EXACT || yv) gstore<ET, R>(eg, gco[c] + (uint32_t)r * grs[c], Energy<R>::add(e[rr][c], d[rr][c]));
             } else {
               if (EXACT || (yv && sto[c] >= 0)) es[y * L + lane + 64 * c] = Energy<R>::add(e[rr][c], d[rr][c]);
             }
