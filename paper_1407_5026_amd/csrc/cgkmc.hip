@@ -177,14 +177,17 @@ int build_tables(const cg_sample_desc& d, int32_t layout, int32_t precision, int
     t.guide[k] = (uint8_t)o;
   }
   if (layout == kRaw || layout == kBig || layout == kFx64) {
-    // 16-bit guide: a bucket [w, w + 2^22) needs the threshold search only if some
-    // threshold of an orbit before the last lies strictly inside it
-    t.guide16.assign(kGuideSize, 0);
-    for (int32_t k = 0; k < kGuideSize; ++k) {
-      const uint64_t w = (uint64_t)k << (32 - kGuideBits), w_end = w + ((uint64_t)1 << (32 - kGuideBits));
-      const int32_t o = t.guide[k];
-      const bool inside = o < n_orb - 1 && (uint64_t)t.thr[o] < w_end;
-      t.guide16[k] = (uint16_t)(o | (inside ? 0x8000 : 0));
+    // 16-bit guide over buckets [w, w + 2^20): the orbit of the bucket's smallest word, and
+    // 0x8000 when the thresholds of two or more orbits before the last lie inside the bucket
+    // (a word of the bucket is then more than one comparison away from its orbit)
+    t.guide16.assign(kGuide16Size, 0);
+    for (int32_t k = 0; k < kGuide16Size; ++k) {
+      const uint64_t w = (uint64_t)k << (32 - kGuide16Bits), w_end = w + ((uint64_t)1 << (32 - kGuide16Bits));
+      int32_t o = 0;
+      while (o < n_orb - 1 && w >= (uint64_t)t.thr[o]) ++o;
+      int32_t inside = 0;
+      for (int32_t q = o; q < n_orb - 1 && (uint64_t)t.thr[q] < w_end; ++q) ++inside;
+      t.guide16[k] = (uint16_t)(o | (inside >= 2 ? 0x8000 : 0));
     }
     // 8 slots per orbit: member m & (size - 1) in slot m, so that slot w3 & 7 is member
     // w3 & (size - 1) for sizes 4 and 8
@@ -749,7 +752,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.vec = off;       off = align_up(off + (size_t)n_vec * 4);
     q.guide = off;     off = align_up(off + kGuideSize);
     q.vec8 = off;      off = align_up(off + (sel16 ? (size_t)n_orb * 64 : 0));
-    q.guide16 = off;   off = align_up(off + (sel16 ? (size_t)kGuideSize * 2 : 0));
+    q.guide16 = off;   off = align_up(off + (sel16 ? (size_t)kGuide16Size * 2 : 0));
     q.tdo64 = off;     off = align_up(off + (bigl ? (size_t)n_orb * 8 : 0));
     q.dft_tw = off;    off = align_up(off + (bigl ? 0 : (size_t)L * 16));
     q.dft_T = off;     off = align_up(off + (bigl ? 0 : (size_t)(H + 1) * L * 8));

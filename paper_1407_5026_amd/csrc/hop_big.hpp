@@ -247,7 +247,7 @@ __host__ __device__ inline BigLds big_lds(int32_t n_orb) {
   BigLds o;
   int32_t b = 0;
   o.thr = b;   b = align16(b + n_orb * 4);
-  o.guide = b; b = align16(b + kGuideSize * 2);
+  o.guide = b; b = align16(b + kGuide16Size * 2);
   o.vec8 = b;  b = align16(b + n_orb * 64);
   o.td = b;    b = align16(b + n_orb * 8);
   o.rec = b;   b = align16(b + kMaxWaves * 32);
@@ -275,11 +275,7 @@ __device__ __forceinline__ void draw_big(uint64_t base, int tid, const FxConst& 
     uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = C.sid, c3 = kTagPropose;
     philox10(c0, c1, c2, c3, C.k0, C.k1);
     const int i = (int)(c0 >> (32 - 2 * LG));
-    const uint32_t g = lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuideBits)));
-    int o = (int)(g & 0x7fffu);
-    if (g & 0x8000u) {
-      while (o < last && c1 >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
-    }
+    const int o = orbit_guided(guide16_at(guide, c1), c1, thr, last);
     const uint64_t v = lds_ld<uint64_t>(vec8 + 8 * (o * 8 + (int)(c3 & 7u)));
     const int vx = (int)(uint32_t)v;
     const int dx = (int)(int16_t)(vx & 0xffff), dy = vx >> 16;
@@ -345,7 +341,7 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
     ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
     ((double*)(smem + lo.td))[k] = S.tdo64[k];
   }
-  for (int k = tid; k < kGuideSize; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
+  for (int k = tid; k < kGuide16Size; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
   for (int k = tid; k < S.n_orb * 8; k += 1024) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
   if (tid < kMaxWaves) {
     rec[2 * tid] = make_uint4(0u, 0u, 0u, ~0u);

@@ -53,7 +53,8 @@ __device__ __forceinline__ float marked(float hi, float lo) {
 struct FxShared {
   uint32_t theta;
   uint32_t pad_;
-  double t;          // Gaussian clock
+  double t;                // Gaussian clock
+  unsigned long long nev;  // label evaluations of the launch (summed over lanes at its end)
 };
 
 template <int L, int NW>
@@ -99,6 +100,26 @@ __device__ __forceinline__ void lds_st(uint32_t a, T v) {
   *(lds_ptr<T>)a = v;
 }
 
+// Orbit of a proposal (step 1's choice of the hop length) from its 32-bit word c1: the first
+// orbit o with c1 < thr[o], the last orbit taking the rest.  g is the 16-bit guide entry of
+// c1's bucket: the orbit of the bucket's smallest word, with 0x8000 set when two or more
+// thresholds lie inside the bucket.  One comparison (no branch) settles every bucket holding
+// at most one threshold; only the flagged buckets (the far orbits' thresholds crowd into the
+// top buckets) continue the search in a loop.
+__device__ __forceinline__ int orbit_guided(uint32_t g, uint32_t c1, uint32_t thr, int last) {
+  int o = (int)(g & 0x7fffu);
+  const uint32_t t = lds_ld<uint32_t>(thr + 4 * o);  // o <= last: inside the table
+  o += (int)((o < last ? 1u : 0u) & (c1 >= t ? 1u : 0u));
+  if (g & 0x8000u) {
+    while (o < last && c1 >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
+  }
+  return o;
+}
+
+__device__ __forceinline__ uint32_t guide16_at(uint32_t guide, uint32_t c1) {
+  return lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuide16Bits)));
+}
+
 // Folded column distance min(|x - x0|, L - |x - x0|) for x, x0 in [0, L), L a power of two.
 template <int L>
 __device__ __forceinline__ int fold_col(int x, int x0) {
@@ -109,7 +130,7 @@ __device__ __forceinline__ int fold_col(int x, int x0) {
 
 // Step 1 for this lane's labels of the chunk starting after `base`: Philox4x32-10 of
 // (label, sample, PROPOSE); site i = mulhi(w0, N) = w0 >> (32 - log2 N); orbit from the
-// 16-bit guide (searched through the thresholds only when the bucket holds one); member
+// 16-bit guide (one threshold comparison; a search only in buckets holding two or more); member
 // w3 & (size - 1), read as w3 & 7 from the 8-slot table; acceptance uniform
 // (2 (w2 >> 9) + 1) 2^-24.
 // Per-sample values the hop loop keeps in scalar registers (read once per launch).
@@ -141,14 +162,11 @@ __device__ __forceinline__ void draw_fx(uint64_t base, int tid, const FxConst& C
   }
   uint32_t g[U];
 #pragma unroll
-  for (int k = 0; k < U; ++k) g[k] = lds_ld<uint16_t>(guide + 2 * (w1[k] >> (32 - kGuideBits)));
+  for (int k = 0; k < U; ++k) g[k] = guide16_at(guide, w1[k]);
   uint64_t v[U];
 #pragma unroll
   for (int k = 0; k < U; ++k) {
-    int o = (int)(g[k] & 0x7fffu);
-    if (g[k] & 0x8000u) {
-      while (o < last && w1[k] >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
-    }
+    const int o = orbit_guided(g[k], w1[k], thr, last);
     v[k] = lds_ld<uint64_t>(vec8 + 8 * (o * 8 + (int)(w3[k] & 7u)));
   }
 #pragma unroll
@@ -250,12 +268,13 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   }
   for (int k = tid; k < G::N / 32; k += NT) occ[k] = S.occ[k];
   for (int k = tid; k < S.n_orb; k += NT) ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
-  for (int k = tid; k < kGuideSize; k += NT) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
+  for (int k = tid; k < kGuide16Size; k += NT) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
   for (int k = tid; k < S.n_orb * 8; k += NT) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
   if (tid < kMaxWaves) info[tid] = make_uint4(0u, 0u, 0u, ~0u);  // no round has this tag
   if (tid == 0) {
     sh->theta = 0u;
     sh->t = t_start;
+    sh->nev = 0ull;
   }
   __syncthreads();
 
@@ -285,7 +304,8 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   FxLabel lbn[U];
   bool pre = false;
   uint32_t theta_cnt = 0;
-  uint32_t round = 0;  // tag of the current evaluation round
+  uint32_t nev = 0;    // this lane's label evaluations (labels at or after dpos in a round)
+  uint32_t round = 0;  // tag of the current evaluation round = rounds of this launch so far
   uint64_t tc0 = 0, tc1 = 0, tc2 = 0, tc3 = 0, tmark = 0;
   constexpr bool timers = TIM;
 #define CG_MARK(acc)                                          \
@@ -342,7 +362,9 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
       const FxLabel& b = lb[k];
       const uint32_t key = (uint32_t)(tid * U + k);
       // not yet decided: key >= dpos (both below 2^31) and no earlier label of the lane accepted
-      const uint32_t open = (((key - dpos) >> 31) ^ 1u) & (found ^ 1u);
+      const uint32_t undec = ((key - dpos) >> 31) ^ 1u;
+      nev += undec;
+      const uint32_t open = undec & (found ^ 1u);
       const uint32_t wi = wis[k], wj = wjs[k];
       const float de = __uint_as_float(wj) - __uint_as_float(wi);
       const uint32_t th = open & wi & ~wj & 1u;  // n_i (1 - n_j) from the value words
@@ -381,10 +403,6 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     win1 = (uint32_t)__builtin_amdgcn_readlane((int)rec.y, wl);
     win2 = (uint32_t)__builtin_amdgcn_readlane((int)rec.z, wl);
     ++round;
-    if (wid == 0) {  // counters read only at the end, by thread 0
-      ++rounds;
-      evaluated += M - dpos;
-    }
     CG_MARK(tc2)
     if (mk != 0u) break;
     // every label of the chunk is rejected
@@ -540,6 +558,7 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   since += (int32_t)(uint32_t)(hops - hops0);
 
   atomicAdd(&sh->theta, theta_cnt);
+  atomicAdd(&sh->nev, (unsigned long long)nev);
   {
     float2* __restrict__ g = (float2*)S.eps;
 #pragma unroll
@@ -560,8 +579,8 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     gs->since_refresh = since;
     gs->status = status;
     gs->sum_p = sum_p;
-    gs->rounds = rounds;
-    gs->evaluated = evaluated;
+    gs->rounds = rounds + round;
+    gs->evaluated = evaluated + sh->nev;
     gs->theta_pass += sh->theta;
     gs->logged = logged;
     if (timers) {

@@ -33,11 +33,11 @@ __host__ __device__ inline Fx64Lds fx64_lds(int32_t L, int32_t n_orb) {
   o.occ = b;   b = align16(b + L * L / 8);
   o.tab = b;   b = align16(b + ((H + 1) * (H + 2) / 2) * 8);
   o.thr = b;   b = align16(b + n_orb * 4);
-  o.guide = b; b = align16(b + kGuideSize * 2);
+  o.guide = b; b = align16(b + kGuide16Size * 2);
   o.vec8 = b;  b = align16(b + n_orb * 64);
   o.info = b;  b = align16(b + 16 * 16);
   o.tag = b;   b = align16(b + 16 * 4);
-  o.ctrl = b;  b = align16(b + 16);
+  o.ctrl = b;  b = align16(b + (int32_t)sizeof(FxShared));
   o.total = b;
   return o;
 }
@@ -87,11 +87,7 @@ __device__ __forceinline__ void draw_fx64(uint64_t base, int tid, const FxConst&
     uint32_t c0 = (uint32_t)lab, c1 = (uint32_t)(lab >> 32), c2 = C.sid, c3 = kTagPropose;
     philox10(c0, c1, c2, c3, C.k0, C.k1);
     const int i = (int)(c0 >> (32 - 2 * G::LG));
-    const uint32_t g = lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuideBits)));
-    int o = (int)(g & 0x7fffu);
-    if (g & 0x8000u) {
-      while (o < last && c1 >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
-    }
+    const int o = orbit_guided(guide16_at(guide, c1), c1, thr, last);
     const int vx = (int)lds_ld<uint32_t>(vec8 + 8 * (o * 8 + (int)(c3 & 7u)));
     const int dx = (int)(int16_t)(vx & 0xffff), dy = vx >> 16;
     const int xi = i & (L - 1), yi = i >> G::LG;
@@ -161,12 +157,13 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
   for (int k = tid; k < G::N / 32; k += 1024) occ[k] = S.occ[k];
   for (int k = tid; k < H1 * (H1 + 1) / 2; k += 1024) tab[k] = ((const double*)S.tabk)[k];
   for (int k = tid; k < S.n_orb; k += 1024) ((uint32_t*)(smem + lo.thr))[k] = S.thr[k];
-  for (int k = tid; k < kGuideSize; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
+  for (int k = tid; k < kGuide16Size; k += 1024) ((uint16_t*)(smem + lo.guide))[k] = S.guide16[k];
   for (int k = tid; k < S.n_orb * 8; k += 1024) ((int2*)(smem + lo.vec8))[k] = ((const int2*)S.vec8)[k];
   if (tid < 16) tag[tid] = ~0u;  // no round carries this tag
   if (tid == 0) {
     sh->theta = 0u;
     sh->t = t_start;
+    sh->nev = 0ull;
   }
   __syncthreads();
 
@@ -187,7 +184,8 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
   Fx64Label lbn[U];  // the next chunk, drawn during a hop's update; valid when next_base == base + M
   uint64_t next_base = ~0ull;
   uint32_t theta_cnt = 0;
-  uint32_t round = 0;
+  uint32_t nev = 0;    // this lane's label evaluations (labels at or after dpos in a round)
+  uint32_t round = 0;  // rounds of this launch so far
 
   for (;;) {
     uint32_t mk = 0u, win0 = 0u, win1 = 0u, win2 = 0u, win3 = 0u;
@@ -212,7 +210,9 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
       for (int k = 0; k < U; ++k) {
         const Fx64Label& b = lb[k];
         const uint32_t key = (uint32_t)(tid * U + k);
-        const uint32_t open = (((key - dpos) >> 31) ^ 1u) & (found ^ 1u);
+        const uint32_t undec = ((key - dpos) >> 31) ^ 1u;
+        nev += undec;
+        const uint32_t open = undec & (found ^ 1u);
         const int bi = (int)(b.ij & 0xffffu), bj = (int)(b.ij >> 16), bdx = (int)b.aidx >> 24;
         const uint32_t wi = occ[bi >> 5], wj = occ[bj >> 5];
         const double ei = lds_ld<double>(b.aidx & 0xffffffu), ej = lds_ld<double>(b.aj);
@@ -254,10 +254,6 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
         win3 = (uint32_t)__builtin_amdgcn_readlane((int)rec.w, wl);
       }
       ++round;
-      if (wid == 0) {  // counters read only at the end, by thread 0
-        ++rounds;
-        evaluated += M - dpos;
-      }
       if (mk != 0u) break;
       base += M;
       dpos = 0;
@@ -361,6 +357,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
   }
 
   atomicAdd(&sh->theta, theta_cnt);
+  atomicAdd(&sh->nev, (unsigned long long)nev);
   {
     double* __restrict__ g = (double*)S.eps;
 #pragma unroll
@@ -380,8 +377,8 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
     gs->H0 = H0;
     gs->status = status;
     gs->sum_p = sum_p;
-    gs->rounds = rounds;
-    gs->evaluated = evaluated;
+    gs->rounds = rounds + round;
+    gs->evaluated = evaluated + sh->nev;
     gs->theta_pass += sh->theta;
     gs->logged = logged;
   }

@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
     ((uint32_t*)(smem + lo.b.thr))[k] = S.thr[k];
     ((double*)(smem + lo.b.td))[k] = S.tdo64[k];
   }
-  for (int k = tid; k < kGuideSize; k += 1024) ((uint16_t*)(smem + lo.b.guide))[k] = S.guide16[k];
+  for (int k = tid; k < kGuide16Size; k += 1024) ((uint16_t*)(smem + lo.b.guide))[k] = S.guide16[k];
   for (int k = tid; k < S.n_orb * 8; k += 1024) ((int2*)(smem + lo.b.vec8))[k] = ((const int2*)S.vec8)[k];
   if (tid < kMaxWaves) rec[tid] = make_uint4(0u, 0u, 0u, ~0u);  // no round has this tag
   if (tid == 0) *tclock = t_start;
@@ -240,11 +240,7 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
       uint32_t c0 = (uint32_t)q, c1 = (uint32_t)(q >> 32), c2 = C.sid, c3 = kTagPropose;
       philox10(c0, c1, c2, c3, C.k0, C.k1);
       const int i = (int)(c0 >> (32 - 2 * LG));
-      const uint32_t gd = lds_ld<uint16_t>(guide + 2 * (c1 >> (32 - kGuideBits)));
-      int o = (int)(gd & 0x7fffu);
-      if (gd & 0x8000u) {
-        while (o < C.last && c1 >= lds_ld<uint32_t>(thr + 4 * o)) ++o;
-      }
+      const int o = orbit_guided(guide16_at(guide, c1), c1, thr, C.last);
       const uint64_t v = lds_ld<uint64_t>(vec8 + 8 * (o * 8 + (int)(c3 & 7u)));
       const int vx = (int)(uint32_t)v;
       const int dx = (int)(int16_t)(vx & 0xffff), dy = vx >> 16;

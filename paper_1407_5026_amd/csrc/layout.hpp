@@ -27,6 +27,10 @@ namespace cg {
 
 constexpr int kGuideBits = 10;
 constexpr int kGuideSize = 1 << kGuideBits;
+// 16-bit guide of the exact-geometry, large-sample and label-parallel kernels: 4096 buckets,
+// entry = orbit of the bucket's smallest word | 0x8000 when two or more thresholds lie inside
+constexpr int kGuide16Bits = 12;
+constexpr int kGuide16Size = 1 << kGuide16Bits;
 constexpr int kMaxWaves = 16;       // 1024 threads of 64 lanes
 constexpr int kMaxCols = 4;         // columns per lane in the row update: L <= 256
 constexpr int kInitBlock = 256;     // threads per block of the init / refresh kernels
@@ -175,7 +179,7 @@ __host__ __device__ inline FxLds fx_lds(int32_t L, int32_t n_orb, int32_t NW = 1
   o.occ = b;   b = align16(b + L * L / 8);
   o.tab = b;   b = align16(b + fx_tab_entries(L, NW) * 4);
   o.thr = b;   b = align16(b + n_orb * 4);
-  o.guide = b; b = align16(b + kGuideSize * 2);
+  o.guide = b; b = align16(b + kGuide16Size * 2);
   o.ctrl = b;  b = align16(b + 64);
   o.info = b;  b = align16(b + kMaxWaves * 16);
   o.vec8 = b;  b = align16(b + n_orb * 64);
