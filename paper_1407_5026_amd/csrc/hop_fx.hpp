@@ -298,6 +298,12 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
   constexpr int kRowTab = NW * P * 4;
   const uint32_t info_lane = opaque(lds0 + lo.info + 16u * (uint32_t)(lane & (kMaxWaves - 1)));
   bool cached = false;
+  // owner test: site l = (y << LG) | x belongs to thread (y % NW) 64 + (x & 63), i.e. to the
+  // thread whose tid - own_off equals l & own_mask
+  constexpr uint32_t own_mask = 63u | ((uint32_t)(NW - 1) << G::LG);
+  const uint32_t own_off = uni((uint32_t)(wid * 64) - ((uint32_t)wid << G::LG));
+  // table row of origin row 0 for this wave's first row (wid + L)
+  const uint32_t tab_w = uni(lds0 + lo.tab + (uint32_t)((wid + L) * P * 4));
   FxLabel lb[U];
   // the chunk after the current one, drawn during a hop's update (the labels do not depend on
   // the configuration): lbn holds chunk base + M when pre is set
@@ -386,8 +392,11 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     // happens before another wave reads it for this round if this round executed no hop
     // from that wave, and then the later tag is simply not this round's.
     const unsigned long long bal = __ballot(found != 0u);
-    if (bal != 0ull) {
-      if (lane == __ffsll(bal) - 1) info[wid] = make_uint4(pub0, pub1, __float_as_uint(pdh), round);
+    {
+      // the lowest accepting lane: found, and no accepting lane below it (a lane count, so
+      // that the test is vector arithmetic and one branch)
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (((found ^ 1u) | below) == 0u) info[wid] = make_uint4(pub0, pub1, __float_as_uint(pdh), round);
     }
     CG_MARK(tc1)
     __syncthreads();
@@ -467,12 +476,13 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     CG_SLOT(21) CG_SLOT(22) CG_SLOT(23) CG_SLOT(24) CG_SLOT(25) CG_SLOT(26) CG_SLOT(27) \
     CG_SLOT(28) CG_SLOT(29) CG_SLOT(30) CG_SLOT(31) default: break;                  \
   }
-      // the owner thread of a site is (y % NW) 64 + (x & 63): one vector compare each
-      if (tid == (((yi & (NW - 1)) << 6) | (xi & 63))) {
+      // the owner thread of a site: one masked vector compare each
+      const uint32_t me = (uint32_t)tid - own_off;
+      if (me == ((uint32_t)hi & own_mask)) {
         const uint32_t n = 0u;
         CG_SLOTS((yi >> G::LW) * NC + (xi >> 6))
       }
-      if (tid == (((yj & (NW - 1)) << 6) | (xj & 63))) {
+      if (me == ((uint32_t)hj & own_mask)) {
         const uint32_t n = 1u;
         CG_SLOTS((yj >> G::LW) * NC + (xj >> 6))
       }
@@ -486,8 +496,8 @@ __global__ void __launch_bounds__(64 * NW) k_hops_fx(const DevSample* __restrict
     // loads are issued before the first store.
     {
       const int xi = hi & (L - 1), yi = hi >> G::LG, xj = hj & (L - 1), yj = hj >> G::LG;
-      const uint32_t rj = lds0 + lo.tab + (uint32_t)((wid - yj + L) * P * 4);
-      const uint32_t ri = lds0 + lo.tab + (uint32_t)((wid - yi + L) * P * 4);
+      const uint32_t rj = tab_w - (uint32_t)(yj * P * 4);
+      const uint32_t ri = tab_w - (uint32_t)(yi * P * 4);
       uint32_t aj[NC], ai[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {

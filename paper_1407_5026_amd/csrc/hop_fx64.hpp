@@ -232,7 +232,8 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
       // the lowest wave whose tag is this round's (keys grow with the thread index); a
       // record is rewritten only by its own wave in a later round
       const unsigned long long bal = __ballot(found != 0u);
-      if (bal != 0ull && lane == __ffsll(bal) - 1) {
+      const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      if (((found ^ 1u) | below) == 0u) {  // found, and no accepting lane below this one
         const uint64_t bits = (uint64_t)__double_as_longlong(pdh);
         info[wid] = make_uint4(pub0, pub1, (uint32_t)bits, (uint32_t)(bits >> 32));
         tag[wid] = round;
