@@ -42,30 +42,35 @@ LDS_WRITE_BPC = 72.0
 LDS_READ_BPC = 224.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_hops_fx_l128_b256_traffic.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1407_5026_amd", "csrc", f) for f in ("hop_fx.hpp", "kernels.hpp", "layout.hpp")]
+# the FP64 form's hop kernel: its own record, over its own sources
+TRAFFIC_FILE64 = os.path.join(ROOT, "profiles", "k_hops_fx64_l128_b256_traffic.json")
+KERNEL_SRCS64 = [os.path.join(ROOT, "paper_1407_5026_amd", "csrc", f)
+                 for f in ("hop_fx64.hpp", "hop_fx.hpp", "kernels.hpp", "layout.hpp")]
 
 
-def kernel_hash() -> str:
+def kernel_hash(srcs=None) -> str:
     """Hash of the hop kernel's sources: a traffic record applies only to the code it measured."""
     import hashlib
 
     h = hashlib.sha256()
-    for p in KERNEL_SRCS:
+    for p in (KERNEL_SRCS if srcs is None else srcs):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def counter_record(kernel: str):
-    """The committed counter record of the hop kernel (HBM bytes per launch from FETCH_SIZE
-    and WRITE_SIZE scaled by a copy kernel of known size; VALU and LDS instructions per hop),
-    or None when it was taken on another kernel instance or the kernel source has changed
+    """The committed counter record of a hop kernel (HBM bytes per launch from FETCH_SIZE
+    and WRITE_SIZE scaled by a copy kernel of known size; VALU, SALU and LDS instructions per
+    hop), or None when it was taken on another kernel instance or the kernel source has changed
     since."""
+    path, srcs = (TRAFFIC_FILE64, KERNEL_SRCS64) if kernel.startswith("k_hops_fx64") else (TRAFFIC_FILE, KERNEL_SRCS)
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash() or not t.get("kernel", "").endswith(kernel):
+    if t.get("kernel_hash") != kernel_hash(srcs) or not t.get("kernel", "").endswith(kernel):
         return None
     return t
 
@@ -501,9 +506,9 @@ def main() -> int:
     }
     rec = counter_record(kernel)
     if rec is not None and "valu_insts_per_hop" in rec:
-        # VALU issue fraction: wave instructions per hop (counter run, hops 8192..12288 of each
-        # sample) x this run's hops/s, against 256 CUs x 1.7 wave instructions per clock (the
-        # probe's FP32 rate) x 2.4 GHz
+        # VALU issue fraction: wave instructions per hop (counter run, the 41st launch: hops
+        # 163840..167936 of each sample) x this run's hops/s, against 256 CUs x 1.7 wave
+        # instructions per clock (the probe's FP32 rate) x 2.4 GHz
         out["valu_frac"] = rec["valu_insts_per_hop"] * value / (256 * 1.7 * 2.4e9)
         out["lds_insts_per_hop"] = rec["lds_insts_per_hop"]
     if r64 is not None:

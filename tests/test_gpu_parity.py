@@ -207,6 +207,27 @@ def test_uneven_batch_fp32_matches_oracle_until_a_near_tie():
         assert int(b.occupation(k).sum()) == s.n_e
 
 
+def test_fp32_l192_batch_matches_oracle_until_a_near_tie():
+    """An FP32 batch up to L = 192, the largest lattice of the one-workgroup kernels, whose value
+    words no longer fit LDS (energies in the arena, 12 rows per wave): both samples execute the
+    oracle's hops until the first label whose FP64 decision FP32 rounding can flip."""
+    cg = require_gpu()
+    samples = [Sample(192, 18432, 1.2, 1.0, 10.0, 0.05, 0.01, 17, 0),
+               Sample(144, 10368, 0.8, 1.0, 10.0, 0.03, 0.005, 17, 1)]
+    hops = 1200
+    b = _batch(cg, samples, precision=cg.CG_FP32_REFRESH, K_refresh=400, log_hops=hops)
+    b.run_hops(hops)
+    for k, s in enumerate(samples):
+        o = oracle_of(s)
+        ol = o.run(hops)
+        eps_max = max(float(np.abs(o.eps()).max()), float(np.abs(b.energies(k)).max()))
+        drift = b.stats(k)["max_drift"]
+        agree = compare_logs_fp32(s, b.hop_log(k), ol, drift, eps_max)
+        say(f"FP32 L={s.L} in a batch up to L=192: {agree} of {hops} hops identical to the oracle")
+        assert drift <= 1e-5
+        assert int(b.occupation(k).sum()) == s.n_e
+
+
 def test_run_time_matches_oracle():
     cg = require_gpu()
     s = serial_small(seed=5)[0]
