@@ -298,6 +298,7 @@ struct Plan {
   bool use_db = false, use_fx = false, use_fx64 = false;
   bool pair = false;  // some sample proposes pair hops: the pair-hop kernel runs the batch
   bool split = false;  // FP32, largest L above 128: pairs in the arena, value words in LDS
+  int32_t max_L = 0;   // the batch's largest lattice
   bool big = false;  // one sample at a time on the whole GPU (large-sample kernel)
   bool wide = false; // one sample at a time on G workgroups, each with a replica (variant 6)
   bool coop = false; // hop kernels run as one cooperative launch per sample (big or wide)
@@ -625,6 +626,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
   int32_t need_full = 0, need_tri = 0, need_exact = 0, max_N = 0;
   // FP32 form, largest lattice above 128: the pairs stay in the arena and only their value
   // words live in LDS (the proposals' random reads), when every sample's fit
+  p.max_L = max_L_all;
   p.split = p.precision == CG_FP32_REFRESH && max_L_all > 128 && !p.pair && !p.big;
   for (int32_t b = 0; b < n && p.split; ++b) {
     const int32_t L = s[b].L, N = L * L, NW = (N + 31) / 32, H = L / 2;
@@ -894,7 +896,7 @@ HopFn pick_pair(int32_t layout, int32_t NC, bool exact) {
 }
 
 HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool exact, bool db, int32_t clock,
-              int32_t block, bool timers, bool split) {
+              int32_t block, bool timers, bool split, bool rows10) {
   if (layout == kCube) {
     switch (NC) {
       case 1: return k_hops3<1>;
@@ -908,8 +910,11 @@ HopFn pick_hop(int32_t precision, int32_t U, int32_t layout, int32_t NC, bool ex
   if (layout == kRaw)
     return clock != CG_CLOCK_DET ? pick_fx<1>(U, NC, block / 64, timers) : pick_fx<0>(U, NC, block / 64, timers);
   if (db) return pick_db(U, NC, exact);
-  if (NC >= 3 && split)  // FP32, L > 128: pairs in the arena, value words in LDS
-    return U == 1 ? k_hops<float, 1, false, 3, 12, false, kModeSplit> : k_hops<float, 2, false, 3, 12, false, kModeSplit>;
+  // FP32, L > 128: pairs in the arena, value words in LDS; up to L = 160 the instance with 10
+  // rows per wave (16 x 10 rows: no wave runs an idle row group)
+  if (NC >= 3 && split)
+    return rows10 ? (U == 1 ? k_hops<float, 1, false, 3, 10, false, kModeSplit> : k_hops<float, 2, false, 3, 10, false, kModeSplit>)
+                  : (U == 1 ? k_hops<float, 1, false, 3, 12, false, kModeSplit> : k_hops<float, 2, false, 3, 12, false, kModeSplit>);
   if (NC >= 3) {  // L > 128: energies in the arena
     if (precision == CG_FP64) return k_hops<double, 1, false, 3, 12, false, kModeGlobal>;
     return k_hops<float, 1, false, 3, 12, false, kModeGlobal>;
@@ -1192,7 +1197,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
   } else {
     c->hop = p.pair ? pick_pair(p.layout, p.NC, p.exact)
                     : pick_hop(p.precision, p.U, p.layout, p.NC, p.exact, p.use_db, p.clock, p.block, p.timers != 0,
-                               p.split);
+                               p.split, p.max_L <= 160);
   }
 
   auto fail = [&](int code) {
