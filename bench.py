@@ -378,6 +378,41 @@ def cubic(cg, torch, L: int, batch: int, hops: int, steps: int) -> dict:
             "cpu_sample": f"3D oracle, sample 0, hops {hops}..{hops + n_cpu} after {hops} untimed"}
 
 
+def pair_hops(cg, torch, batch: int, pair: float, hops: int, steps: int) -> dict:
+    """Pair hops (a label proposes two electrons moving at once with probability `pair`: the
+    multi-electron extension of sections "Code performance" and "Conclusions"): the headline
+    parameters in the FP64 form from the random start, one untimed step of `hops` hops per
+    sample, then `steps` timed steps, on the pair-hop kernel; beside it the same batch with
+    single hops only on the generic FP64 kernel it derives from (variant 1)."""
+    import dataclasses
+
+    from workloads import headline
+
+    out = {"batch": batch, "L": 128, "T": 0.02, "pair_probability": pair, "hops_per_step": hops, "steps": steps}
+    for key, p, variant in (("pair", pair, 0), ("single", 0.0, 1)):
+        samples = [dataclasses.replace(s, pair=p) for s in headline(batch)]
+        b = cg.Batch(samples, cg.make_opts(precision=cg.CG_FP64, variant=variant))
+        b.run_hops(hops)
+        torch.cuda.synchronize()
+        s0 = [b.stats(k) for k in range(batch)]
+        b.kernel_time()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.run_hops(hops)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        hop_ms, hop_n, _, _ = b.kernel_time()
+        s1 = [b.stats(k) for k in range(batch)]
+        b.close()
+        n_h = sum(x["hops"] - y["hops"] for x, y in zip(s1, s0))
+        out[key] = {"hops_per_s": n_h / dt, "mean_launch_ms": hop_ms / max(hop_n, 1),
+                    "m_bar": sum(x["s_last"] - y["s_last"] for x, y in zip(s1, s0)) / max(n_h, 1),
+                    "rounds_per_hop": sum(x["rounds"] - y["rounds"] for x, y in zip(s1, s0)) / max(n_h, 1)}
+    out["pair"]["kernel"] = "k_hops_pair<true, 2, 8, true>"
+    out["single"]["kernel"] = "k_hops<double, 1, true, 2, 8, true, kModeLds>"
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +460,11 @@ def main() -> int:
     ap.add_argument("--cubic-steps", type=int, default=20)
     ap.add_argument("--l64-hops", type=int, default=200_000,
                     help="hops per sample of the 256-sample L = 64 temperature-grid batch (0 = none)")
+    ap.add_argument("--pair", type=float, default=0.1,
+                    help="pair-hop probability of the pair-hop leg (FP64, headline parameters; 0 = none)")
+    ap.add_argument("--pair-steps", type=int, default=5)
+    ap.add_argument("--legs", nargs="*", default=None,
+                    help="run only these legs: l64 large wide wide3 uneven cubic pair (default: all)")
     ap.add_argument("--phase-steps", type=int, default=4,
                     help="steps of the phase-timer run that splits a hop into W_R and W_U (0 = none)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -528,6 +568,21 @@ def main() -> int:
         out["phase_split_fp32"] = leg("phase timers (W_R / W_U per hop)",
                                       lambda: phase_split(cg, torch, samples, args))
     if not args.no_legs:
+        want = (lambda name: True) if args.legs is None else (lambda name: name in args.legs)
+        if not want("l64"):
+            args.l64_hops = 0
+        if not want("large"):
+            args.large_L = []
+        if not want("wide"):
+            args.wide_L = []
+        if not want("wide3"):
+            args.wide3_L = []
+        if not want("uneven"):
+            args.uneven = 0
+        if not want("cubic"):
+            args.cubic_L = 0
+        if not want("pair"):
+            args.pair = 0.0
         if args.l64_hops:
             out["batched_l64_fp32"] = leg(f"256 samples L=64 over the T grid, {args.l64_hops} hops each",
                                           lambda: batched_l64(cg, torch, args.l64_hops, 8192))
@@ -560,6 +615,10 @@ def main() -> int:
         if args.cubic_L:
             out["cubic_fp64"] = leg(f"cubic batch L={args.cubic_L}",
                                     lambda: cubic(cg, torch, args.cubic_L, args.batch, args.cubic_hops, args.cubic_steps))
+        if args.pair > 0:
+            out["pair_hops_fp64"] = leg(f"pair hops p={args.pair} L=128",
+                                        lambda: pair_hops(cg, torch, args.batch, args.pair, args.hops_per_step,
+                                                          args.pair_steps))
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

@@ -102,7 +102,7 @@ typedef struct cg_run_opts {
                           executed hops do not depend on M                               */
   int32_t block;       /* threads per workgroup: 1024 (0 = 1024); 512 selects the
                           exact-geometry kernel's 8-wave form (same hops and energies
-                          bit for bit, 8-11% fewer hops/s at L = 128); CG_EINVAL otherwise */
+                          bit for bit, 13% fewer hops/s at L = 128); CG_EINVAL otherwise */
   int32_t K_refresh;   /* FP32 form: hops between FP64 refreshes (>= 1); 0 = 4096       */
   int32_t clock_mode;  /* CG_CLOCK_DET, CG_CLOCK_GAUSS or CG_CLOCK_GAMMA                 */
   int32_t log_hops;    /* per-sample capacity of the executed-hop log (0 = no log)       */
