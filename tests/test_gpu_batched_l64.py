@@ -55,7 +55,9 @@ def test_batched_l64_fp32_until_the_first_near_tie():
         assert st["refreshes"] == hops // K and st["max_drift"] <= 1e-5
         agree = compare_logs_fp32(s, b.hop_log(k), o.run(hops), st["max_drift"], eps_max)
         say(f"batched L=64 FP32 sample {k} T={s.T}: {agree} of {hops} hops identical to the oracle")
-        assert agree >= 20
+        # measured: every compared hop identical (6144 of 6144 for each checked sample); an FP32
+        # near-tie within the first half would be a new finding to look at
+        assert agree >= hops // 2
 
 
 def test_batched_l64_fp32_full_run():

@@ -76,7 +76,9 @@ def test_headline_fp32_full_size():
         eps_max = max(float(np.abs(o.eps()).max()), float(np.abs(b.energies(k)).max()))
         agree = compare_logs_fp32(s, b.hop_log(k), o.run(STEP * STEPS), b.stats(k)["max_drift"], eps_max)
         say(f"headline FP32 sample {k}: {agree} of {STEP * STEPS} hops identical to the oracle")
-        assert agree >= 20
+        # measured: every compared hop identical (8192 of 8192 for each checked sample); an FP32
+        # near-tie within the first half would be a new finding to look at
+        assert agree >= STEP * STEPS // 2
         _check_sampled_energies(b, k, s, 1e-5)
 
 

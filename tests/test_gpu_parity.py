@@ -421,7 +421,9 @@ def test_fp32_matches_oracle_until_a_near_tie(variant, L, M):
     drift = b.stats(0)["max_drift"]
     agree = compare_logs_fp32(s, b.hop_log(0), o.run(hops), drift, eps_max)
     say(f"FP32 variant {variant} L={L} M={M}: {agree} of {hops} hops identical to the oracle")
-    assert agree >= 20
+    # measured: every compared hop identical (3000 of 3000 for every kernel, L and M); an FP32
+    # near-tie within the first half would be a new finding to look at
+    assert agree >= hops // 2
     assert drift <= 1e-5
 
 
