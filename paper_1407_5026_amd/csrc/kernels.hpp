@@ -314,8 +314,9 @@ enum EnergyMode : int {
   kModeLds = 1,     // energies in LDS, updated in place (FP64: value = storage)
   kModeGlobal = 2,  // energies in the arena (HBM/L2), updated in place; for lattices whose
                     // energies do not fit LDS
-  kModeSplit = 3,   // FP32 pairs in the arena, updated in place by the row update, and their
-                    // value words in LDS for the proposals' random reads
+  kModeSplit = 3,   // FP32: value words in LDS, updated in place, and the pairs' low parts in
+                    // a contiguous arena array (4 bytes per site each way per hop); the
+                    // pairs are rebuilt at the end of a launch
 };
 
 template <typename R, int U, bool TRI, int NC, int RPW, bool EXACT, int MODE>
@@ -388,7 +389,19 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
     } else if constexpr (MODE == kModeLds) {
       for (int k = tid; k < N; k += 1024) es[k] = g[k];
     } else if constexpr (MODE == kModeSplit) {
+      // value words of every site; the low parts of the lane's own sites (the only ones it
+      // reads and writes until the end of the launch)
       for (int k = tid; k < N; k += 1024) ev[k] = Energy<R>::value(g[k]);
+      R* __restrict__ lw = (R*)S.mirror;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int y = wid + NW * r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int x = lane + 64 * c;
+          if (y < L && x < L) lw[y * L + x] = ((const R*)&g[y * L + x])[1];
+        }
+      }
     }
     const R* gt = (const R*)S.tabk;
     for (int k = tid; k < S.ntab; k += 1024) tab[k] = gt[k];
@@ -565,19 +578,37 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
       // sample's sink word (after the N energies) instead, so no access needs a lane branch.
       // Formed here, not hoisted out of the hop loop (one address per site would occupy
       // registers for the whole launch).
+      // (kModeSplit: offsets into the low-part array, 4 bytes per site, sink after N)
+      constexpr int kEs = MODE == kModeSplit ? (int)sizeof(R) : (int)sizeof(ET);
       uint32_t gco[NC], grs[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const bool xv = sto[c] >= 0;
-        gco[c] = opaque(xv ? (uint32_t)((wid * L + lane + 64 * c) * (int)sizeof(ET)) : (uint32_t)(N * (int)sizeof(ET)));
-        grs[c] = xv ? (uint32_t)(NW * L * (int)sizeof(ET)) : 0u;
+        gco[c] = opaque(xv ? (uint32_t)((wid * L + lane + 64 * c) * kEs) : (uint32_t)(N * kEs));
+        grs[c] = xv ? (uint32_t)(NW * L * kEs) : 0u;
       }
-      // rows in groups of RG: every load of a group is issued before its first use
-      constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : (MODE == kModeGlobal || MODE == kModeSplit) ? 2 : 4;
+      // kModeSplit: LDS byte address of the lane's value word in column block c and its first
+      // row, and the stride to its next row (the sink word past the lattice's edge)
+      using lds_r = __attribute__((address_space(3))) R*;
+      uint32_t lco[NC], lrs[NC];
+      if constexpr (MODE == kModeSplit) {
+        const uint32_t ev0 = (uint32_t)(uintptr_t)(lds_r)ev;
+        const uint32_t lsink = (uint32_t)(uintptr_t)(lds_r)(R*)&sh->dummy;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const bool xv = sto[c] >= 0;
+          lco[c] = opaque(xv ? ev0 + (uint32_t)((wid * L + lane + 64 * c) * (int)sizeof(R)) : lsink);
+          lrs[c] = xv ? (uint32_t)(NW * L * (int)sizeof(R)) : 0u;
+        }
+      }
+      const gbl_ptr<R> lwg = (gbl_ptr<R>)S.mirror;  // kModeSplit: the low parts
+      // rows in groups of RG: every load of a group is issued before its first use (the split
+      // mode takes one row at a time, which measured fastest)
+      constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : MODE == kModeGlobal ? 2 : MODE == kModeSplit ? 1 : 4;
 #pragma unroll
       for (int r0 = 0; r0 < RPW; r0 += RG) {
         R d[RG][NC];
-        ET e[MODE == kModeReg ? 1 : RG][NC];
+        ET e[MODE == kModeReg ? 1 : RG][NC];  // kModeSplit: (value from LDS, low part)
 #pragma unroll
         for (int rr = 0; rr < RG; ++rr) {
           const int y = wid + NW * (r0 + rr);
@@ -596,6 +627,11 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
             d[rr][c] = tab[kj] - tab[ki];
             if constexpr (MODE == kModeLds) {
               if (EXACT || (yv && sto[c] >= 0)) e[rr][c] = es[y * L + lane + 64 * c];
+            } else if constexpr (MODE == kModeSplit) {
+              if (EXACT || yv) {
+                ((R*)&e[rr][c])[0] = *(lds_r)(lco[c] + (uint32_t)(r0 + rr) * lrs[c]);
+                ((R*)&e[rr][c])[1] = gload<R, R>(lwg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
+              }
             } else if constexpr (MODE != kModeReg) {
               if (EXACT || yv) e[rr][c] = gload<ET, R>(eg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
             }
@@ -615,9 +651,8 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
             } else if constexpr (MODE == kModeSplit) {
               if (EXACT || yv) {
                 const ET a = Energy<R>::add(e[rr][c], d[rr][c]);
-                gstore<ET, R>(eg, gco[c] + (uint32_t)r * grs[c], a);
-                R* dst = (EXACT || sto[c] >= 0) ? ev + (y * L + lane + 64 * c) : (R*)&sh->dummy;
-                *dst = Energy<R>::value(a);
+                gstore<R, R>(lwg, gco[c] + (uint32_t)r * grs[c], ((const R*)&a)[1]);
+                *(lds_r)(lco[c] + (uint32_t)r * lrs[c]) = Energy<R>::value(a);
               }
             } else if constexpr (MODE == kModeGlobal) {
               if (EXACT || yv) gstore<ET, R>(eg, gco[c] + (uint32_t)r * grs[c], Energy<R>::add(e[rr][c], d[rr][c]));
@@ -652,6 +687,23 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         for (int c = 0; c < NC; ++c) {
           const int x = lane + 64 * c;
           if (y < L && x < L) g[y * L + x] = E[r][c];
+        }
+      }
+    } else if constexpr (MODE == kModeSplit) {
+      // the pairs of the lane's own sites: value words and low parts both last written by it
+      const R* __restrict__ lw = (const R*)S.mirror;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        const int y = wid + NW * r;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int x = lane + 64 * c;
+          if (y < L && x < L) {
+            ET a;
+            ((R*)&a)[0] = ev[y * L + x];
+            ((R*)&a)[1] = lw[y * L + x];
+            g[y * L + x] = a;
+          }
         }
       }
     }
