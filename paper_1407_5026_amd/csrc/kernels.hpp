@@ -605,6 +605,19 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
       // rows in groups of RG: every load of a group is issued before its first use (the split
       // mode takes one row at a time, which measured fastest)
       constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : MODE == kModeGlobal ? 2 : MODE == kModeSplit ? 1 : 4;
+      // the split mode loads a row's low parts PD rows ahead of its update (a load of the
+      // arena is issued three rows' work before its value is needed)
+      constexpr int PD = MODE == kModeSplit ? 3 : 0;
+      R lpre[PD > 0 ? PD : 1][NC];
+      if constexpr (PD > 0) {
+#pragma unroll
+        for (int q = 0; q < PD && q < RPW; ++q) {
+          const int y = wid + NW * q;
+#pragma unroll
+          for (int c = 0; c < NC; ++c)
+            lpre[q][c] = (EXACT || y < L) ? gload<R, R>(lwg, gco[c] + (uint32_t)q * grs[c]) : R(0);
+        }
+      }
 #pragma unroll
       for (int r0 = 0; r0 < RPW; r0 += RG) {
         R d[RG][NC];
@@ -630,7 +643,10 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
             } else if constexpr (MODE == kModeSplit) {
               if (EXACT || yv) {
                 ((R*)&e[rr][c])[0] = *(lds_r)(lco[c] + (uint32_t)(r0 + rr) * lrs[c]);
-                ((R*)&e[rr][c])[1] = gload<R, R>(lwg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
+                if constexpr (PD > 0)
+                  ((R*)&e[rr][c])[1] = lpre[(r0 + rr) % (PD > 0 ? PD : 1)][c];
+                else
+                  ((R*)&e[rr][c])[1] = gload<R, R>(lwg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
               }
             } else if constexpr (MODE != kModeReg) {
               if (EXACT || yv) e[rr][c] = gload<ET, R>(eg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
@@ -653,6 +669,11 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
                 const ET a = Energy<R>::add(e[rr][c], d[rr][c]);
                 gstore<R, R>(lwg, gco[c] + (uint32_t)r * grs[c], ((const R*)&a)[1]);
                 *(lds_r)(lco[c] + (uint32_t)r * lrs[c]) = Energy<R>::value(a);
+              }
+              if constexpr (PD > 0) {
+                const int y2 = wid + NW * (r + PD);
+                if (r + PD < RPW && (EXACT || y2 < L))
+                  lpre[r % (PD > 0 ? PD : 1)][c] = gload<R, R>(lwg, gco[c] + (uint32_t)(r + PD) * grs[c]);
               }
             } else if constexpr (MODE == kModeGlobal) {
               if (EXACT || yv) gstore<ET, R>(eg, gco[c] + (uint32_t)r * grs[c], Energy<R>::add(e[rr][c], d[rr][c]));
