@@ -99,7 +99,7 @@ struct HostTables {
   std::vector<uint32_t> thr_u;    // pair hops: floor(2^32 * cumulative orbit size / n_vec)
   std::vector<int32_t> vec;
   std::vector<uint8_t> guide;
-  std::vector<uint16_t> guide16;  // kRaw: orbit | 0x8000 when a threshold lies inside the bucket
+  std::vector<uint16_t> guide16;  // orbit | 0x8000 when two or more thresholds lie inside the bucket
   std::vector<int32_t> vec8;      // kRaw: [n_orb][8][2] member (dx, dy) packed, FP32 1/|d| bits
   std::vector<double> tdo64;      // kBig: FP64 1/|d| per orbit
   std::vector<double> tab64;  // full folded table
