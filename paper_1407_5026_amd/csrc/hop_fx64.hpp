@@ -61,6 +61,38 @@ struct Fx64Geo {
 
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
+// Folded row distances of step 3b.  For a wave w and an origin row y0, the wave's row
+// y = w + 16 r lies at folded distance a = min(v, L - v) from y0, v = (d + 16 r) mod L with
+// d = (w - y0) mod L; row d of the table holds a for r < L / 16 and, beside it, a (a + 1) / 2,
+// the start of row a of the triangle-ordered 1/r table.  Read with scalar loads, it takes
+// the per-row distance arithmetic off the CU's shared scalar unit.
+template <int L>
+struct RowFold {
+  uint32_t a[L][L / 16];
+  uint32_t t[L][L / 16];
+};
+template <int L>
+constexpr RowFold<L> make_row_fold() {
+  RowFold<L> f{};
+  for (int d = 0; d < L; ++d)
+    for (int r = 0; r < L / 16; ++r) {
+      const int v = (d + 16 * r) & (L - 1);
+      const int a = v < L - v ? v : L - v;
+      f.a[d][r] = (uint32_t)a;
+      f.t[d][r] = (uint32_t)((a * (a + 1)) >> 1);
+    }
+  return f;
+}
+__constant__ const RowFold<64> kRowFold64 = make_row_fold<64>();
+__constant__ const RowFold<128> kRowFold128 = make_row_fold<128>();
+template <int L>
+__device__ __forceinline__ const RowFold<L>& row_fold() {
+  if constexpr (L == 64)
+    return kRowFold64;
+  else
+    return kRowFold128;
+}
+
 // a (a + 1) / 2: start of row a of the triangle-ordered table
 __device__ __forceinline__ int tri_start(int a) { return (a * (a + 1)) >> 1; }
 
@@ -309,14 +341,15 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
         tiv[c] = tri_start(ci[c]);
       }
       const uint32_t tb = lds0 + lo.tab;
+      const RowFold<L>& F = row_fold<L>();
+      const int dj = (wid - yj) & (L - 1), di = (wid - yi) & (L - 1);
 #pragma unroll
       for (int r0 = 0; r0 < RPW; r0 += RG) {
         double a[RG][NC], bv[RG][NC];
 #pragma unroll
         for (int rr = 0; rr < RG; ++rr) {
-          const int y = wid + NW * (r0 + rr);
-          const int ayj = uni(fold(y - yj, L)), ayi = uni(fold(y - yi, L));
-          const int tyj = uni(tri_start(ayj)), tyi = uni(tri_start(ayi));
+          const int ayj = (int)F.a[dj][r0 + rr], ayi = (int)F.a[di][r0 + rr];
+          const int tyj = (int)F.t[dj][r0 + rr], tyi = (int)F.t[di][r0 + rr];
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             const int kj = cj[c] >= ayj ? tj[c] + ayj : tyj + cj[c];
