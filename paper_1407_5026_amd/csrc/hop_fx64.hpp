@@ -63,13 +63,13 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // Folded row distances of step 3b.  For a wave w and an origin row y0, the wave's row
 // y = w + 16 r lies at folded distance a = min(v, L - v) from y0, v = (d + 16 r) mod L with
-// d = (w - y0) mod L; row d of the table holds a for r < L / 16 and, beside it, a (a + 1) / 2,
-// the start of row a of the triangle-ordered 1/r table.  Read with scalar loads, it takes
-// the per-row distance arithmetic off the CU's shared scalar unit.
+// d = (w - y0) mod L; row d of the table holds 8 a for r < L / 16 and, beside it,
+// 8 a (a + 1) / 2, the byte offset of row a of the triangle-ordered 1/r table.  Read with
+// scalar loads, it takes the per-row distance arithmetic off the CU's shared scalar unit.
 template <int L>
 struct RowFold {
-  uint32_t a[L][L / 16];
-  uint32_t t[L][L / 16];
+  uint32_t a8[L][L / 16];
+  uint32_t t8[L][L / 16];
 };
 template <int L>
 constexpr RowFold<L> make_row_fold() {
@@ -78,8 +78,8 @@ constexpr RowFold<L> make_row_fold() {
     for (int r = 0; r < L / 16; ++r) {
       const int v = (d + 16 * r) & (L - 1);
       const int a = v < L - v ? v : L - v;
-      f.a[d][r] = (uint32_t)a;
-      f.t[d][r] = (uint32_t)((a * (a + 1)) >> 1);
+      f.a8[d][r] = (uint32_t)(8 * a);
+      f.t8[d][r] = (uint32_t)(8 * ((a * (a + 1)) >> 1));
     }
   return f;
 }
@@ -328,17 +328,21 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
     }
 
     // step 3b on the owned sites: eps += 1/r_lj - 1/r_li from the triangle table.  The
-    // column distances are per lane, a row's distance is the same for the whole wave.
+    // column distances are per lane, a row's distance is the same for the whole wave.  The
+    // entry of distances (a, b) sits at tri(max) + min, and since tri(a) = a (a + 1) / 2
+    // grows with a, tri(max(a, b)) = max(tri(a), tri(b)): three vector operations per
+    // entry, all in byte units.
     {
       const int xi = hi & (L - 1), yi = hi >> G::LG, xj = hj & (L - 1), yj = hj >> G::LG;
-      int cj[NC], ci[NC], tj[NC], tiv[NC];
+      uint32_t cj[NC], ci[NC], tj[NC], tiv[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int x = lane + 64 * c;
-        cj[c] = fold(x - xj, L);
-        ci[c] = fold(x - xi, L);
-        tj[c] = tri_start(cj[c]);
-        tiv[c] = tri_start(ci[c]);
+        const int fj = fold(x - xj, L), fi = fold(x - xi, L);
+        cj[c] = 8u * (uint32_t)fj;
+        ci[c] = 8u * (uint32_t)fi;
+        tj[c] = 8u * (uint32_t)tri_start(fj);
+        tiv[c] = 8u * (uint32_t)tri_start(fi);
       }
       const uint32_t tb = lds0 + lo.tab;
       const RowFold<L>& F = row_fold<L>();
@@ -348,14 +352,14 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
         double a[RG][NC], bv[RG][NC];
 #pragma unroll
         for (int rr = 0; rr < RG; ++rr) {
-          const int ayj = (int)F.a[dj][r0 + rr], ayi = (int)F.a[di][r0 + rr];
-          const int tyj = (int)F.t[dj][r0 + rr], tyi = (int)F.t[di][r0 + rr];
+          const uint32_t ayj = F.a8[dj][r0 + rr], ayi = F.a8[di][r0 + rr];
+          const uint32_t tyj = F.t8[dj][r0 + rr], tyi = F.t8[di][r0 + rr];
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            const int kj = cj[c] >= ayj ? tj[c] + ayj : tyj + cj[c];
-            const int ki = ci[c] >= ayi ? tiv[c] + ayi : tyi + ci[c];
-            a[rr][c] = lds_ld<double>(tb + 8u * (uint32_t)kj);
-            bv[rr][c] = lds_ld<double>(tb + 8u * (uint32_t)ki);
+            const uint32_t kj = (tj[c] > tyj ? tj[c] : tyj) + (cj[c] < ayj ? cj[c] : ayj);
+            const uint32_t ki = (tiv[c] > tyi ? tiv[c] : tyi) + (ci[c] < ayi ? ci[c] : ayi);
+            a[rr][c] = lds_ld<double>(tb + kj);
+            bv[rr][c] = lds_ld<double>(tb + ki);
           }
         }
         // while the first group's loads are in flight: draw the next chunk if needed
