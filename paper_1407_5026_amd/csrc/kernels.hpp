@@ -199,6 +199,15 @@ template <> struct Energy<float> {
 template <bool TRI>
 __device__ __forceinline__ int tri_of(int a) { return (a * (a + 1)) >> 1; }
 
+// Table index of the folded distances (ay, ax) in step 3b with tay = tri(ay), tax = tri(ax)
+// already formed (TRI): the triangle entry tri(max) + min is max(tay, tax) + min(ay, ax),
+// since tri(a) = a (a + 1) / 2 grows with a; otherwise the row-major ay H1 + ax.
+template <bool TRI>
+__device__ __forceinline__ int tidx_pre(int ay, int tay, int ax, int tax, int H1) {
+  if (TRI) return (tay > tax ? tay : tax) + (ay < ax ? ay : ax);
+  return ay * H1 + ax;
+}
+
 // Gaussian clock increment of step 3c for hop number h with m serial proposals:
 // Box-Muller on the CLOCK stream, mean m/Gamma, deviation sqrt(m)/Gamma, clamped at 0.
 __device__ __noinline__ double gauss_dt(uint64_t h, uint64_t m, uint32_t sid, uint32_t k0, uint32_t k1,
@@ -629,14 +638,8 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
           const int ayj = yv ? fold(y - yj, L) : 0, ayi = yv ? fold(y - yi, L) : 0;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
-            int kj, ki;
-            if (TRI) {
-              kj = cjx[c] >= ayj ? tjx[c] + ayj : tri_of<TRI>(ayj) + cjx[c];
-              ki = cix[c] >= ayi ? tix[c] + ayi : tri_of<TRI>(ayi) + cix[c];
-            } else {
-              kj = ayj * H1 + cjx[c];
-              ki = ayi * H1 + cix[c];
-            }
+            const int kj = tidx_pre<TRI>(ayj, TRI ? tri_of<TRI>(ayj) : 0, cjx[c], tjx[c], H1);
+            const int ki = tidx_pre<TRI>(ayi, TRI ? tri_of<TRI>(ayi) : 0, cix[c], tix[c], H1);
             d[rr][c] = tab[kj] - tab[ki];
             if constexpr (MODE == kModeLds) {
               if (EXACT || (yv && sto[c] >= 0)) e[rr][c] = es[y * L + lane + 64 * c];
