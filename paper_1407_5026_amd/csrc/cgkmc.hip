@@ -1274,6 +1274,7 @@ int cg_create(cg_ctx** out, const cg_sample_desc* samples, int32_t n, const cg_r
     s.nu = (double)d.n_electrons / (double)N;
     s.W = d.W;
     s.T = d.T;
+    s.mrT = -1.0 / d.T;
     s.E = d.E;
     // labels arrive at Gamma / (1 - pair): the clock's rate (Gamma itself without pair hops)
     s.Gamma = t.Gamma / (1.0 - d.pair);
@@ -1556,6 +1557,7 @@ int cg_set_TE(cg_ctx* c, int32_t b, double T, double E) {
   c->desc[b].E = E;
   DevSample& s = c->dev[b];
   s.T = T;
+  s.mrT = -1.0 / T;
   s.E = E;
   s.T32 = (float)T;
   s.E32 = (float)E;

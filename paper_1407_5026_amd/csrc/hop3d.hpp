@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
   __syncthreads();
 
   const uint32_t k0 = uni(S.seed_lo), k1 = uni(S.seed_hi), sid = uni(S.sample_id);
-  const double T = uni(S.T), E = uni(S.E);
+  const double mrT = uni(S.mrT), E = uni(S.E);
   const int64_t log_cap = uni((int64_t)S.log_cap);
   const uint64_t s_end = uni(ra.time_mode ? label_at_time(t_end, Gamma) : (uint64_t)0);
   uint32_t theta_cnt = 0, round = 0;
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops3(const DevSample* __restr
           ++theta_cnt;
           dH0 = (eps[lj] - eps[li]) - lr;
           const double dH = dH0 - E * (double)ldx;
-          acc = dH <= 0.0 || lu < exp(-dH / T);
+          acc = dH <= 0.0 || lu < exp(dH * mrT);
         }
       }
       const unsigned long long bal = __ballot(acc);

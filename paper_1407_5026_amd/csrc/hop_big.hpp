@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
   C.last = uni(S.n_orb - 1);
   C.Ef = 0.f;
   C.mTln2 = 0.f;
-  const double Ef = uni(S.E), Tt = uni(S.T), Gamma = uni(S.Gamma);
+  const double Ef = uni(S.E), mrT = uni(S.mrT), Gamma = uni(S.Gamma);
   const int64_t log_cap = uni((int64_t)S.log_cap);
   const double* __restrict__ tab = S.tab64;
   constexpr int H1 = L / 2 + 1;
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(1024) k_hops_big(const DevSample* __restrict__
         const double dh0 = (ej - ei) - b.td;
         const double dH = dh0 - Ef * (double)b.dx;
         bool a = dH <= 0.0;
-        if (th && !a) a = b.u < exp(-dH / Tt);
+        if (th && !a) a = b.u < exp(dH * mrT);
         theta_cnt += th ? 1u : 0u;
         if (th && a) {
           first = k;

@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
   C.last = uni(S.n_orb - 1);
   C.Ef = 0.f;
   C.mTln2 = 0.f;
-  const double Ed = uni(S.E), T = uni(S.T), Gamma = uni(S.Gamma);
+  const double Ed = uni(S.E), mrT = uni(S.mrT), Gamma = uni(S.Gamma);
   const int64_t log_cap = uni((int64_t)S.log_cap);
   const uint64_t s_end = uni((ra.time_mode && CLOCK == 0) ? label_at_time(t_end, Gamma) : (uint64_t)0);
   // this lane's value words: slot pair q = (s0, s0 + 1) at ev_lane + 1024 q
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(1024) k_hops_fx64(const DevSample* __restrict_
         const uint32_t th = open & (wi >> (bi & 31)) & ~(wj >> (bj & 31)) & 1u;
         const double dh0 = (ej - ei) - b.td;
         const double dH = dh0 - Ed * (double)bdx;
-        const double pth = exp(-dH / T);
+        const double pth = exp(dH * mrT);
         const uint32_t acc = th & ((dH <= 0.0) | (b.u < pth) ? 1u : 0u);
         theta_cnt += th;
         pub0 = acc ? b.ij : pub0;

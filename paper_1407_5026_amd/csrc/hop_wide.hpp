@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
   C.last = uni(S.n_orb - 1);
   C.Ef = 0.f;
   C.mTln2 = 0.f;
-  const double Ef = uni(S.E), Tt = uni(S.T), Gamma = uni(S.Gamma);
+  const double Ef = uni(S.E), mrT = uni(S.mrT), Gamma = uni(S.Gamma);
   const int64_t log_cap = uni((int64_t)S.log_cap);
   const uint64_t s_end = uni((ra.time_mode && CLOCK == 0) ? label_at_time(t_end, Gamma) : (uint64_t)0);
   bool cached = false;
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(1024) k_hops_wide(const DevSample* __restrict_
         if (th) {
           const double dH = ((eps[b.j] - eps[b.i]) - b.td) - Ef * (double)b.dx;
           bool a = dH <= 0.0;
-          if (!a) a = b.u < exp(-dH / Tt);
+          if (!a) a = b.u < exp(dH * mrT);
           if (a) mine = key;
         }
         theta_cnt += th ? 1u : 0u;

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops_wide3(const DevSample* __
   __syncthreads();
 
   const uint32_t k0 = uni(S.seed_lo), k1 = uni(S.seed_hi), sid = uni(S.sample_id);
-  const double T = uni(S.T), E = uni(S.E);
+  const double mrT = uni(S.mrT), E = uni(S.E);
   const int64_t log_cap = uni((int64_t)S.log_cap);
   const uint64_t s_end = uni(ra.time_mode ? label_at_time(t_end, Gamma) : (uint64_t)0);
   uint32_t theta_cnt = 0, round = 0;
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kCubeThreads) k_hops_wide3(const DevSample* __
         if (th) {
           ++theta_cnt;
           const double dH = ((eps[lb.j] - eps[lb.i]) - lb.r) - E * (double)lb.dx;
-          acc = dH <= 0.0 || lb.u < exp(-dH / T);
+          acc = dH <= 0.0 || lb.u < exp(dH * mrT);
         }
       }
       // the lowest accepted key of the workgroup (keys grow with the thread index), then the

@@ -67,7 +67,7 @@ template <> __device__ __forceinline__ float accept_uniform<float>(uint32_t w2, 
 
 // Metropolis factor of Eq. 2: accept iff dH <= 0 or u < exp(-dH/T).
 __device__ __forceinline__ bool metropolis(double dH, double u, const DevSample& S) {
-  return dH <= 0.0 || u < exp(-dH / S.T);
+  return dH <= 0.0 || u < exp(dH * S.mrT);
 }
 __device__ __forceinline__ bool metropolis(float dH, float u, const DevSample& S) {
   return dH <= 0.0f || u < __expf(-dH * S.invT32);
@@ -79,7 +79,7 @@ __device__ __forceinline__ bool metropolis_nb(float dH, float u, bool, const Dev
 }
 __device__ __forceinline__ bool metropolis_nb(double dH, double u, bool th, const DevSample& S) {
   bool a = dH <= 0.0;
-  if (th && !a) a = u < exp(-dH / S.T);
+  if (th && !a) a = u < exp(dH * S.mrT);
   return a;
 }
 __device__ __forceinline__ double field(const DevSample& S, double) { return S.E; }

@@ -74,6 +74,7 @@ struct DevSample {
   int32_t log2M, pad2_;       // the sample's PR width M = 2^log2M (iterations p = ceil(m / M))
   uint32_t seed_lo, seed_hi, sample_id, magic_L;  // magic_L = ceil(2^32 / L)
   double nu, W, T, E, Gamma;
+  double mrT;  // -1/T: the FP64 kernels form the thermal factor exp(-dH/T) as exp(dH mrT)
   float T32, E32, invT32, mTln2_32;  // mTln2_32 = -T ln 2 (acceptance thresholds)
   SampleState* st;
   void* eps;
