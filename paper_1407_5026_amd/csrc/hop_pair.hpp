@@ -55,6 +55,7 @@ struct PairLabel {
   int32_t t1, t2, te, tjl, til, tjk;  // 1/r table indices: d1, d2, ik, jl, il, jk
   int32_t dx, kind;
   double u;
+  double lam;  // -T ln u, formed when the label is drawn
 };
 
 // First orbit o with w < thr[o] (the last orbit takes the rest), from a lower bound o0.
@@ -95,6 +96,7 @@ __device__ __forceinline__ void draw_pair_label(uint64_t lab, const DevSample& S
   b.dx = dx1;
   b.kind = 0;
   b.u = accept_uniform<double>(c2, c3);
+  b.lam = -S.T * log(b.u);
   if (S.thr_pair == 0u) return;
   uint32_t p0 = (uint32_t)lab, p1 = (uint32_t)(lab >> 32), p2 = S.sample_id, p3 = kTagPair;
   philox10(p0, p1, p2, p3, S.seed_lo, S.seed_hi);
@@ -232,7 +234,18 @@ __global__ void __launch_bounds__(1024) k_hops_pair(const DevSample* __restrict_
         dh0 = (dh0 + h2) + hint;
       }
       const double dH = dh0 - Ef * (double)lb.dx;
-      acc = th && metropolis_nb(dH, lb.u, th, S);
+      // Metropolis as dH < lam = -T ln u: beyond 1e-12 (T + lam) of the threshold the
+      // comparison decides as the exponential test does (the roundings of lam, of dH/T and of
+      // the exponential move it by a few units of 1e-16 (T + lam)); nearer to it the lane
+      // evaluates the exponential test itself (a branch that practically no wave takes)
+      const double gap = dH - lb.lam;
+      bool a = gap < 0.0;
+      const bool near = fabs(gap) <= 1e-12 * (S.T + lb.lam);
+      if (__ballot(near) != 0ull) {
+        asm volatile("" ::: "memory");  // a real branch: keeps this path from being speculated
+        if (near) a = metropolis_nb(dH, lb.u, true, S);
+      }
+      acc = th && a;
       theta_cnt += th ? 1u : 0u;
     }
     // the wave's lowest accepting lane publishes its label; the round's minimum key over
