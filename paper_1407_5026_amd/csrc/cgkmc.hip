@@ -771,7 +771,7 @@ int make_plan(const cg_sample_desc* s, int32_t n, const cg_run_opts* o, Plan& p,
     q.log_to = off;    off = align_up(off + (size_t)p.log_cap * 4);
     // the large-sample kernel's energy mirror; FP32 batches above L = 128 with their value
     // words in LDS: the pairs' low parts during a launch (N + 1 floats, the last a sink)
-    q.mirror = off;    off = align_up(off + (bigl ? (size_t)N * 8 : (p.split ? (size_t)(N + 1) * 4 : 0)));
+    q.mirror = off;    off = align_up(off + (bigl ? (size_t)N * 8 : (p.split ? kSplitLoBytes : 0)));
     q.sel = off;       off = align_up(off + (bigl ? sizeof(OccSelect) : 0));
     q.mirror2 = off;   off = align_up(off + (bigl ? (size_t)N * 8 : 0));
     q.occ2 = off;      off = align_up(off + (bigl ? (size_t)NW * 4 : 0));

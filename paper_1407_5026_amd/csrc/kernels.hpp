@@ -324,8 +324,9 @@ enum EnergyMode : int {
   kModeGlobal = 2,  // energies in the arena (HBM/L2), updated in place; for lattices whose
                     // energies do not fit LDS
   kModeSplit = 3,   // FP32: value words in LDS, updated in place, and the pairs' low parts in
-                    // a contiguous arena array (4 bytes per site each way per hop); the
-                    // pairs are rebuilt at the end of a launch
+                    // each thread's own 16-byte groups in the arena (4 bytes per site each
+                    // way per hop, four sites per access); the pairs are rebuilt at the end
+                    // of a launch
 };
 
 template <typename R, int U, bool TRI, int NC, int RPW, bool EXACT, int MODE>
@@ -407,8 +408,8 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         const int y = wid + NW * r;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const int x = lane + 64 * c;
-          if (y < L && x < L) lw[y * L + x] = ((const R*)&g[y * L + x])[1];
+          const int x = lane + 64 * c, s = r * NC + c;
+          if (y < L && x < L) lw[4 * (1024 * (s >> 2) + tid) + (s & 3)] = ((const R*)&g[y * L + x])[1];
         }
       }
     }
@@ -610,22 +611,20 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
           lrs[c] = xv ? (uint32_t)(NW * L * (int)sizeof(R)) : 0u;
         }
       }
-      const gbl_ptr<R> lwg = (gbl_ptr<R>)S.mirror;  // kModeSplit: the low parts
       // rows in groups of RG: every load of a group is issued before its first use (the split
       // mode takes one row at a time, which measured fastest)
       constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : MODE == kModeGlobal ? 2 : MODE == kModeSplit ? 1 : 4;
-      // the split mode loads a row's low parts PD rows ahead of its update (a load of the
-      // arena is issued three rows' work before its value is needed)
-      constexpr int PD = MODE == kModeSplit ? 3 : 0;
-      R lpre[PD > 0 ? PD : 1][NC];
-      if constexpr (PD > 0) {
+      // kModeSplit: the lane's low parts, slot s = r NC + c in component s % 4 of its group
+      // s / 4 (16 bytes, 1024 g + tid in float4 units).  Three groups are in flight: group
+      // g + 3 is loaded once group g is stored, three rows' work before its first use.  A
+      // slot of a site past the lattice's edge is the lane's own, so no access needs a sink.
+      constexpr int SPL = RPW * NC, NG = (SPL + 3) / 4, NB = 3;
+      using lgrp_t = __attribute__((ext_vector_type(4))) float;
+      const gbl_ptr<lgrp_t> lw4 = (gbl_ptr<lgrp_t>)S.mirror;
+      lgrp_t lgrp[NB], lout = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (MODE == kModeSplit) {
 #pragma unroll
-        for (int q = 0; q < PD && q < RPW; ++q) {
-          const int y = wid + NW * q;
-#pragma unroll
-          for (int c = 0; c < NC; ++c)
-            lpre[q][c] = (EXACT || y < L) ? gload<R, R>(lwg, gco[c] + (uint32_t)q * grs[c]) : R(0);
-        }
+        for (int g = 0; g < NB && g < NG; ++g) lgrp[g] = lw4[1024 * g + tid];
       }
 #pragma unroll
       for (int r0 = 0; r0 < RPW; r0 += RG) {
@@ -644,13 +643,9 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
             if constexpr (MODE == kModeLds) {
               if (EXACT || (yv && sto[c] >= 0)) e[rr][c] = es[y * L + lane + 64 * c];
             } else if constexpr (MODE == kModeSplit) {
-              if (EXACT || yv) {
-                ((R*)&e[rr][c])[0] = *(lds_r)(lco[c] + (uint32_t)(r0 + rr) * lrs[c]);
-                if constexpr (PD > 0)
-                  ((R*)&e[rr][c])[1] = lpre[(r0 + rr) % (PD > 0 ? PD : 1)][c];
-                else
-                  ((R*)&e[rr][c])[1] = gload<R, R>(lwg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
-              }
+              const int s = (r0 + rr) * NC + c;
+              if (EXACT || yv) ((R*)&e[rr][c])[0] = *(lds_r)(lco[c] + (uint32_t)(r0 + rr) * lrs[c]);
+              ((R*)&e[rr][c])[1] = lgrp[(s >> 2) % NB][s & 3];
             } else if constexpr (MODE != kModeReg) {
               if (EXACT || yv) e[rr][c] = gload<ET, R>(eg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
             }
@@ -668,15 +663,13 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
               R* dst = (EXACT || (yv && sto[c] >= 0)) ? ev + (y * L + lane + 64 * c) : (R*)&sh->dummy;
               *dst = Energy<R>::value(E[r][c]);
             } else if constexpr (MODE == kModeSplit) {
-              if (EXACT || yv) {
-                const ET a = Energy<R>::add(e[rr][c], d[rr][c]);
-                gstore<R, R>(lwg, gco[c] + (uint32_t)r * grs[c], ((const R*)&a)[1]);
-                *(lds_r)(lco[c] + (uint32_t)r * lrs[c]) = Energy<R>::value(a);
-              }
-              if constexpr (PD > 0) {
-                const int y2 = wid + NW * (r + PD);
-                if (r + PD < RPW && (EXACT || y2 < L))
-                  lpre[r % (PD > 0 ? PD : 1)][c] = gload<R, R>(lwg, gco[c] + (uint32_t)(r + PD) * grs[c]);
+              const int s = r * NC + c, gi = s >> 2;
+              const ET a = Energy<R>::add(e[rr][c], d[rr][c]);
+              lout[s & 3] = ((const R*)&a)[1];
+              if (EXACT || yv) *(lds_r)(lco[c] + (uint32_t)r * lrs[c]) = Energy<R>::value(a);
+              if ((s & 3) == 3 || s == SPL - 1) {
+                lw4[1024 * gi + tid] = lout;
+                if (gi + NB < NG) lgrp[gi % NB] = lw4[1024 * (gi + NB) + tid];
               }
             } else if constexpr (MODE == kModeGlobal) {
               if (EXACT || yv) gstore<ET, R>(eg, gco[c] + (uint32_t)r * grs[c], Energy<R>::add(e[rr][c], d[rr][c]));
@@ -721,11 +714,11 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
         const int y = wid + NW * r;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-          const int x = lane + 64 * c;
+          const int x = lane + 64 * c, s = r * NC + c;
           if (y < L && x < L) {
             ET a;
             ((R*)&a)[0] = ev[y * L + x];
-            ((R*)&a)[1] = lw[y * L + x];
+            ((R*)&a)[1] = lw[4 * (1024 * (s >> 2) + tid) + (s & 3)];
             g[y * L + x] = a;
           }
         }

@@ -29,6 +29,11 @@ constexpr int kGuideBits = 10;
 constexpr int kGuideSize = 1 << kGuideBits;
 // 16-bit guide of the exact-geometry, large-sample and label-parallel kernels: 4096 buckets,
 // entry = orbit of the bucket's smallest word | 0x8000 when two or more thresholds lie inside
+// Split mode (FP32 pairs, value words in LDS): each thread keeps its sites' low parts in
+// its own 16-byte groups of four slots during a launch, group g of thread t at float index
+// 4 (1024 g + t); at most 36 slots (9 groups) per thread
+constexpr int kSplitGroups = 9;
+constexpr size_t kSplitLoBytes = (size_t)kSplitGroups * 1024 * 16;
 constexpr int kGuide16Bits = 12;
 constexpr int kGuide16Size = 1 << kGuide16Bits;
 constexpr int kMaxWaves = 16;       // 1024 threads of 64 lanes
