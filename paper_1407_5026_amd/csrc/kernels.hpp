@@ -615,10 +615,10 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
       // mode takes one row at a time, which measured fastest)
       constexpr int RG = (MODE == kModeReg && EXACT) ? RPW : MODE == kModeGlobal ? 2 : MODE == kModeSplit ? 1 : 4;
       // kModeSplit: the lane's low parts, slot s = r NC + c in component s % 4 of its group
-      // s / 4 (16 bytes, 1024 g + tid in float4 units).  Three groups are in flight: group
-      // g + 3 is loaded once group g is stored, three rows' work before its first use.  A
-      // slot of a site past the lattice's edge is the lane's own, so no access needs a sink.
-      constexpr int SPL = RPW * NC, NG = (SPL + 3) / 4, NB = 3;
+      // s / 4 (16 bytes, 1024 g + tid in float4 units).  Four groups are in flight: group
+      // g + 4 is loaded once group g is stored, about four rows' work before its first use.
+      // A slot of a site past the lattice's edge is the lane's own, so no access needs a sink.
+      constexpr int SPL = RPW * NC, NG = (SPL + 3) / 4, NB = 4;
       using lgrp_t = __attribute__((ext_vector_type(4))) float;
       const gbl_ptr<lgrp_t> lw4 = (gbl_ptr<lgrp_t>)S.mirror;
       lgrp_t lgrp[NB], lout = {0.f, 0.f, 0.f, 0.f};

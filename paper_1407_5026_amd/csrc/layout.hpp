@@ -95,7 +95,8 @@ struct DevSample {
   const uint16_t* guide16;  // orbit at each bucket start | 0x8000 if two or more thresholds lie inside
   const double* tdo64;    // large-sample kernel: FP64 1/|d| per orbit
   double* mirror;         // large-sample kernel: global copy of the energies for the proposals;
-                          // FP32 batches above L = 128: the low parts (float) during a launch
+                          // FP32 batches above L = 128: the low parts (float) during a launch,
+                          // in each thread's own 16-byte groups (kSplitGroups)
   double* mirror2;        // large-sample kernel: the second copy (odd hops of a launch)
   uint32_t* occ2;         // large-sample kernel: second copy of the occupation words
   uint32_t* bar;          // large-sample kernel: grid-barrier words, one per 128-byte line
