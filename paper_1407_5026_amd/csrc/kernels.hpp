@@ -644,7 +644,11 @@ __global__ void __launch_bounds__(1024) k_hops(const DevSample* __restrict__ sam
               if (EXACT || (yv && sto[c] >= 0)) e[rr][c] = es[y * L + lane + 64 * c];
             } else if constexpr (MODE == kModeSplit) {
               const int s = (r0 + rr) * NC + c;
-              if (EXACT || yv) ((R*)&e[rr][c])[0] = *(lds_r)(lco[c] + (uint32_t)(r0 + rr) * lrs[c]);
+              // a row past the lattice's edge updates an arbitrary (but defined) value into
+              // the lane's unused slot; no code is spent on it
+              R v = __builtin_nondeterministic_value(R(0));
+              if (EXACT || yv) v = *(lds_r)(lco[c] + (uint32_t)(r0 + rr) * lrs[c]);
+              ((R*)&e[rr][c])[0] = v;
               ((R*)&e[rr][c])[1] = lgrp[(s >> 2) % NB][s & 3];
             } else if constexpr (MODE != kModeReg) {
               if (EXACT || yv) e[rr][c] = gload<ET, R>(eg, gco[c] + (uint32_t)(r0 + rr) * grs[c]);
